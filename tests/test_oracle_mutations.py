@@ -1,0 +1,55 @@
+"""The pins catch plausible mistakes: each case plants one mistake in a copy of
+the oracle's C source (on the CPU), builds it, and runs the pin suite against
+that build, which must fail."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "lbt1_oracle.c")
+
+MUTATIONS = {
+    "dropped_quadratic_term": ("4.5 * eu * eu", "0.0 * eu * eu"),
+    "wrong_sign_u2": ("1.0 - 1.5 * (u * u + v * v)", "1.0 + 1.5 * (u * u + v * v)"),
+    "momentum_uses_k_not_inverse": ("us += OR_EX[ik] * f;", "us += OR_EX[k] * f;"),
+    "paper_wall_drops_density": ("f = OR_W[ik] * R[x];", "f = OR_W[ik] * 1.0;"),
+    "force_not_applied": ("double u = (U[s] + fx) / r;", "double u = U[s] / r;"),
+    "halfway_returns_wrong_direction": ("f = oracle_feq(k, r, u, v);", "f = oracle_feq(ik, r, u, v);"),
+    "periodic_wrap_transposed": ("ip = (ip + nx) % nx;", "ip = (ip + ny) % ny;"),
+    "eu_uses_u_twice": ("double eu = OR_EX[k] * u + OR_EY[k] * v;", "double eu = OR_EX[k] * u + OR_EY[k] * u;"),
+    "fixed_nodes_updated": ("if (fl != OR_FLUID) {", "if (fl == OR_SOLID) {"),
+    "neighbour_reversed_in_y": ("int jp = j + OR_EY[k];", "int jp = j - OR_EY[k];"),
+    "source_density_from_target": ("double r = R[s];", "double r = R[x];"),
+    "inverse_table_swapped": ("{0, 3, 4, 1, 2, 7, 8, 5, 6}", "{0, 3, 4, 1, 2, 8, 7, 5, 6}"),
+    "diagonal_weight": ("1.0 / 36.0, 1.0 / 36.0};", "1.0 / 36.0, 1.0 / 9.0};"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_planted_mistake_fails_a_pin(name, tmp_path):
+    old, new = MUTATIONS[name]
+    text = open(SRC).read()
+    assert text.count(old) == 1, name
+    src = tmp_path / "mutant.c"
+    src.write_text(text.replace(old, new))
+    lib = tmp_path / "libmutant.so"
+    subprocess.run(["gcc", "-O1", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-fopenmp",
+                    "-o", str(lib), str(src), "-lm"], check=True)
+    env = dict(os.environ, LBT1_ORACLE_LIB=str(lib))
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                       env=env, cwd=ROOT, capture_output=True, text=True, timeout=600)
+    assert r.returncode != 0, f"mutation {name} survived the pins:\n{r.stdout[-2000:]}"
+
+
+def test_control_unmodified_copy_passes(tmp_path):
+    lib = tmp_path / "libcopy.so"
+    subprocess.run(["gcc", "-O1", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-fopenmp",
+                    "-o", str(lib), SRC, "-lm"], check=True)
+    env = dict(os.environ, LBT1_ORACLE_LIB=str(lib))
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                       env=env, cwd=ROOT, capture_output=True, text=True, timeout=600)
+    assert r.returncode == 0, r.stdout[-2000:]

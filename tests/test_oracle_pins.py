@@ -1,0 +1,404 @@
+"""Pins of the CPU oracle against what the paper and mathematics fix.
+
+Each test names the passage it follows.  None of them re-types the oracle's
+update: the expected values come from exact rational arithmetic, closed-form
+solutions, conservation laws, the independent brute-force BGK solver, or the
+paper's worked example and printed numbers (``tests/golden``).
+
+P1  equilibrium and lattice tables    -- exact moment identities (section 2)
+P2  uniform state / force             -- fixed point, j_n = j_0 + n F
+P3  shear wave                        -- exact decay (2 + cos k)/3 per step
+P4  full 2-D step                     -- brute-force BGK at tau = 1 (Eq. lbm vs Eq. LBMTau1)
+P5  channel flow                      -- steady parabola, L^-2 error law, 1-D recurrence
+P6  paper wall rule mass budget       -- exact leak identity
+P7  periodic conservation             -- mass, momentum + N F
+P8  north-wall worked example         -- tests/golden/north_wall.txt
+P9  memory formulas                   -- tests/golden/memory_example.txt
+"""
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import bgk
+from oracle import closed_forms as cf
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+EPS = np.finfo(np.float64).eps
+
+
+def _rng(seed):
+    return np.random.default_rng(seed)
+
+
+def _random_state(rng, ny, nx, drho=1e-2, du=1e-2):
+    rho = 1.0 + drho * rng.standard_normal((ny, nx))
+    jx = rho * du * rng.standard_normal((ny, nx))
+    jy = rho * du * rng.standard_normal((ny, nx))
+    return rho, jx, jy
+
+
+# ----------------------------------------------------------------- P1 tables, f^eq
+def test_p1_tables_are_d2q9():
+    ex, ey, inv, w = oracle.tables()
+    # velocity set printed in section 2, k = 0..8
+    assert list(zip(ex, ey)) == [(0, 0), (1, 0), (0, 1), (-1, 0), (0, -1),
+                                 (1, 1), (-1, 1), (-1, -1), (1, -1)]
+    exact = [Fraction(w_).limit_denominator(100) for w_ in w]
+    assert exact == [Fraction(4, 9)] + [Fraction(1, 9)] * 4 + [Fraction(1, 36)] * 4
+    assert sum(exact) == 1
+    for k in range(9):
+        assert (ex[inv[k]], ey[inv[k]]) == (-ex[k], -ey[k])
+        assert w[inv[k]] == w[k]
+        assert inv[inv[k]] == k
+    # lattice isotropy: sum w e_a e_b = delta_ab / 3 (c_s^2 = 1/3, Eq. viscosity)
+    assert sum(e * e * q for e, q in zip(ex, exact)) == Fraction(1, 3)
+    assert sum(a * b * q for a, b, q in zip(ex, ey, exact)) == 0
+
+
+def test_p1_equilibrium_moments_exact_rational():
+    """sum f = rho, sum e f = rho u, sum e e f = rho/3 I + rho u u, in exact arithmetic."""
+    ex, ey, _, w = oracle.tables()
+    wq = [Fraction(x).limit_denominator(100) for x in w]
+    rho, u, v = Fraction(7, 5), Fraction(3, 50), Fraction(-2, 25)
+
+    def feq(k):
+        eu = ex[k] * u + ey[k] * v
+        return wq[k] * rho * (1 - Fraction(3, 2) * (u * u + v * v) + 3 * eu + Fraction(9, 2) * eu * eu)
+
+    f = [feq(k) for k in range(9)]
+    assert sum(f) == rho
+    assert sum(ex[k] * f[k] for k in range(9)) == rho * u
+    assert sum(ey[k] * f[k] for k in range(9)) == rho * v
+    assert sum(ex[k] ** 2 * f[k] for k in range(9)) == rho / 3 + rho * u * u
+    assert sum(ey[k] ** 2 * f[k] for k in range(9)) == rho / 3 + rho * v * v
+    assert sum(ex[k] * ey[k] * f[k] for k in range(9)) == rho * u * v
+    # and the oracle's floating-point f^eq is the same function
+    for k in range(9):
+        assert oracle.feq(k, float(rho), float(u), float(v)) == pytest.approx(float(f[k]), rel=4 * EPS, abs=0)
+
+
+# ----------------------------------------------------------------- P2 uniform state
+@pytest.mark.parametrize("wall", [0, 1])
+def test_p2_uniform_state_fixed_point_and_force(wall):
+    ny, nx = 6, 5
+    rho = np.full((ny, nx), 1.25)
+    jx = np.full((ny, nx), 0.03)
+    jy = np.full((ny, nx), -0.02)
+    r, u, v = oracle.run(rho, jx, jy, 10, periodic=3, wall=wall)
+    assert np.allclose(r, rho, rtol=20 * EPS, atol=0)
+    assert np.allclose(u, jx, rtol=0, atol=40 * EPS)
+    assert np.allclose(v, jy, rtol=0, atol=40 * EPS)
+    F = (2.5e-5, -1e-5)
+    r, u, v = oracle.run(rho, jx, jy, 10, periodic=3, force=F, wall=wall)
+    assert np.abs(r - rho).max() < 1e-15
+    assert np.abs(u - (jx + 10 * F[0])).max() < 1e-16
+    assert np.abs(v - (jy + 10 * F[1])).max() < 1e-16
+
+
+# ----------------------------------------------------------------- P3 shear wave
+@pytest.mark.parametrize("A", [1e-3, 0.1])
+@pytest.mark.parametrize("m", [1, 3])
+def test_p3_shear_wave_exact_decay(A, m):
+    """x-independent jx = A sin(k y): all |u|^2 terms cancel, so it decays by (2 + cos k)/3."""
+    ny, nx, n = 24, 4, 50
+    kwave = 2 * math.pi * m / ny
+    y = np.arange(ny)[:, None] * np.ones((1, nx))
+    rho = np.ones((ny, nx))
+    jx = A * np.sin(kwave * y)
+    r, u, v = oracle.run(rho, jx, np.zeros((ny, nx)), n, periodic=3)
+    lam = cf.shear_wave_factor(kwave)
+    assert np.abs(u - A * lam ** n * np.sin(kwave * y)).max() < 1e-15 * max(1.0, A * 10)
+    assert np.abs(r - 1).max() < 1e-14
+    assert np.abs(v).max() < 1e-15
+    # the transposed wave tests the other axis
+    r, u, v = oracle.run(rho.T.copy(), np.zeros((nx, ny)), jx.T.copy(), n, periodic=3)
+    assert np.abs(v - A * lam ** n * np.sin(kwave * y.T)).max() < 1e-15 * max(1.0, A * 10)
+    assert np.abs(u).max() < 1e-15
+
+
+def test_p3_small_k_viscosity_is_one_sixth():
+    """(2 + cos k)/3 = 1 - k^2/6 + O(k^4): diffusion with nu = c_s^2 (tau - 1/2) = 1/6."""
+    ny, nx, n = 256, 3, 20
+    kwave = 2 * math.pi / ny
+    y = np.arange(ny)[:, None] * np.ones((1, nx))
+    _, u, _ = oracle.run(np.ones((ny, nx)), 1e-4 * np.sin(kwave * y), np.zeros((ny, nx)), n, periodic=3)
+    lam = (np.abs(u).max() / 1e-4) ** (1.0 / n)
+    nu = (1 - lam) / kwave ** 2
+    assert nu == pytest.approx(1.0 / 6.0, rel=1e-3)
+
+
+# ----------------------------------------------------------------- P4 brute-force BGK
+def _cavity_flags(ny, nx, obstacle=True):
+    flags = np.zeros((ny, nx), np.uint8)
+    flags[0, :] = oracle.SOLID
+    flags[:, 0] = oracle.SOLID
+    flags[:, -1] = oracle.SOLID
+    flags[-1, 1:-1] = oracle.FIXED
+    if obstacle:
+        flags[ny // 2, nx // 2] = oracle.SOLID
+    return flags
+
+
+@pytest.mark.parametrize("wall", [0, 1])
+def test_p4_bgk_tau1_equals_moments_only(wall):
+    rng = _rng(4)
+    ny, nx = 7, 9
+    flags = _cavity_flags(ny, nx)
+    rho, jx, jy = _random_state(rng, ny, nx)
+    F = (1e-3, -2e-3)
+    ref = bgk.BGK(rho, jx, jy, flags, periodic=0, force=F, wall=wall)
+    r, u, v = rho, jx, jy
+    worst = 0.0
+    for _ in range(200):
+        ref.step()
+        r, u, v = oracle.step(r, u, v, flags, 0, F, wall)
+        br, bu, bv = ref.moments()
+        worst = max(worst, np.abs(br - r).max(), np.abs(bu - u).max(), np.abs(bv - v).max())
+    assert worst < 5e-15
+
+
+@pytest.mark.parametrize("periodic", [1, 2, 3])
+@pytest.mark.parametrize("wall", [0, 1])
+def test_p4_bgk_tau1_periodic_axes_and_obstacles(periodic, wall):
+    rng = _rng(10 + periodic)
+    ny, nx = 6, 7
+    flags = (rng.random((ny, nx)) < 0.2).astype(np.uint8)
+    rho, jx, jy = _random_state(rng, ny, nx)
+    F = (3e-4, 1e-4)
+    ref = bgk.BGK(rho, jx, jy, flags, periodic=periodic, force=F, wall=wall)
+    br, bu, bv = ref.run(60)
+    r, u, v = oracle.run(rho, jx, jy, 60, flags, periodic, F, wall)
+    assert max(np.abs(br - r).max(), np.abs(bu - u).max(), np.abs(bv - v).max()) < 5e-15
+
+
+def test_p4_wall_rules_differ():
+    """The two wall readings are different operators (guards against a rule being ignored)."""
+    rng = _rng(5)
+    flags = _cavity_flags(7, 9)
+    rho, jx, jy = _random_state(rng, 7, 9)
+    a = oracle.step(rho, jx, jy, flags, 0, (0, 0), 0)
+    b = oracle.step(rho, jx, jy, flags, 0, (0, 0), 1)
+    assert np.abs(a[1] - b[1]).max() > 1e-4
+
+
+# ----------------------------------------------------------------- P5 channel flow
+@pytest.mark.parametrize("ny", [5, 8, 16, 33])
+@pytest.mark.parametrize("wall", [0, 1])
+def test_p5_poiseuille_closed_form_is_fixed_point(ny, wall):
+    nx, F = 4, 2.5e-5
+    flags = np.zeros((ny, nx), np.uint8)
+    flags[0] = flags[-1] = oracle.SOLID
+    ueq = cf.poiseuille_ueq_paper(ny, F) if wall == 0 else cf.poiseuille_ueq_halfway(ny, F)
+    jx = np.repeat((ueq - F)[:, None], nx, axis=1)
+    jx[0] = jx[-1] = 0.0
+    rho = np.ones((ny, nx))
+    r, u, v = oracle.step(rho, jx, np.zeros((ny, nx)), flags, 1, (F, 0), wall)
+    assert np.abs(u - jx)[1:-1].max() < 1e-12 * ueq.max()
+    assert np.abs(r - 1).max() < 4 * EPS
+    assert np.abs(v).max() < 4 * EPS      # rho/6 - rho/6 up to rounding
+
+
+@pytest.mark.parametrize("wall", [0, 1])
+def test_p5_channel_from_rest_matches_1d_recurrence_and_converges(wall):
+    """The 64 x 32 channel (periodic x, walls on rows 0 and 31, F = 1e-6) run 10,000 steps."""
+    ny, nx, F, n = 32, 64, 1e-6, 10000
+    flags = np.zeros((ny, nx), np.uint8)
+    flags[0] = flags[-1] = oracle.SOLID
+    r, u, v = oracle.run(np.ones((ny, nx)), np.zeros((ny, nx)), np.zeros((ny, nx)), n, flags, 1, (F, 0), wall)
+    j1 = cf.channel_1d(ny, F, wall, n)
+    assert np.abs(u - j1[:, None])[1:-1].max() < 1e-12 * np.abs(j1).max()
+    assert np.abs(u - u[:, :1]).max() < 1e-18                      # x-independent
+    ueq = cf.poiseuille_ueq_paper(ny, F) if wall == 0 else cf.poiseuille_ueq_halfway(ny, F)
+    # slowest mode decays as ((2 + cos(pi/31))/3)^n; after 10,000 steps ~3.7e-8 of u_max remains
+    assert np.abs((u + F) - ueq[:, None])[1:-1].max() < 1e-7 * ueq.max()
+
+
+def test_p5_error_scales_as_inverse_square_of_size():
+    """Section 3: the centre-velocity error falls as L^-2; here with the exact prefactor 400/(3 H^2)."""
+    F = 2.5e-5
+    errs = []
+    for ny in (17, 25, 33, 49):
+        H = ny - 1
+        flags = np.zeros((ny, 3), np.uint8)
+        flags[0] = flags[-1] = oracle.SOLID
+        ueq = cf.poiseuille_ueq_paper(ny, F)
+        # start near the steady state and relax the remaining rounding with a few steps
+        jx = np.repeat((ueq - F)[:, None], 3, axis=1)
+        jx[0] = jx[-1] = 0.0
+        r, u, _ = oracle.run(np.ones((ny, 3)), jx, np.zeros((ny, 3)), 200, flags, 1, (F, 0), 0)
+        c = H // 2
+        measured = u[c, 0] / r[c, 0]
+        exact = cf.poiseuille_analytic(ny, F)[c]
+        e = 100 * abs(measured - exact) / abs(exact)
+        assert e == pytest.approx(cf.centre_error_percent_paper(ny), rel=1e-8)
+        errs.append((H, e))
+    slope = np.polyfit(np.log([h for h, _ in errs]), np.log([e for _, e in errs]), 1)[0]
+    assert slope == pytest.approx(-2.0, abs=1e-6)
+    # the 200 x 100 channel of section 3: 400 / (3 * 99^2) percent
+    assert cf.centre_error_percent_paper(100) == pytest.approx(0.0136041, rel=1e-5)
+
+
+# ----------------------------------------------------------------- P6 paper wall rule mass budget
+def test_p6_paper_wall_mass_leak_identity():
+    """Under Eq. feqnoslip a wall link returns w_k rho(x) instead of the f^eq_k(x) it received,
+    so the mass changes by sum over wall links of (w_k rho(x) - f^eq_k(x)); half-way keeps it."""
+    rng = _rng(6)
+    ny, nx = 8, 10
+    flags = np.zeros((ny, nx), np.uint8)
+    flags[0] = flags[-1] = oracle.SOLID
+    flags[:, 0] = flags[:, -1] = oracle.SOLID
+    flags[3, 4] = flags[4, 6] = oracle.SOLID
+    rho, jx, jy = _random_state(rng, ny, nx, 1e-2, 3e-2)
+    F = (1e-4, 2e-4)
+    fluid = flags == oracle.FLUID
+    for _ in range(30):
+        leak = 0.0
+        feq = bgk.equilibrium(rho, (jx + F[0]) / rho, (jy + F[1]) / rho)
+        for j in range(ny):
+            for i in range(nx):
+                if not fluid[j, i]:
+                    continue
+                for k in range(1, 9):
+                    if flags[j + bgk.EY[k], i + bgk.EX[k]] == oracle.SOLID:
+                        leak += bgk.W[k] * rho[j, i] - feq[k, j, i]
+        m0 = rho[fluid].sum()
+        rho, jx, jy = oracle.step(rho, jx, jy, flags, 0, F, 0)
+        assert rho[fluid].sum() - m0 == pytest.approx(leak, abs=1e-13)   # leak itself ~1e-4
+    rho, jx, jy = _random_state(rng, ny, nx, 1e-2, 3e-2)
+    m0 = rho[fluid].sum()
+    r, _, _ = oracle.run(rho, jx, jy, 30, flags, 0, F, 1)
+    assert abs(r[fluid].sum() - m0) / m0 < 8 * EPS * 30
+
+
+# ----------------------------------------------------------------- P7 periodic conservation
+@pytest.mark.parametrize("wall", [0, 1])
+def test_p7_periodic_conservation(wall):
+    rng = _rng(7)
+    ny, nx, n = 12, 10, 40
+    rho, jx, jy = _random_state(rng, ny, nx)
+    F = (2e-5, -3e-5)
+    r, u, v = oracle.run(rho, jx, jy, n, None, 3, F, wall)
+    N = ny * nx
+    m0 = rho.sum()
+    assert abs(r.sum() - m0) / m0 < 8 * EPS * n
+    assert u.sum() == pytest.approx(jx.sum() + n * N * F[0], abs=1e-12)
+    assert v.sum() == pytest.approx(jy.sum() + n * N * F[1], abs=1e-12)
+
+
+def test_p7_halfway_obstacles_conserve_mass():
+    rng = _rng(8)
+    ny, nx, n = 12, 10, 40
+    flags = (rng.random((ny, nx)) < 0.25).astype(np.uint8)
+    rho, jx, jy = _random_state(rng, ny, nx)
+    fluid = flags == 0
+    r, _, _ = oracle.run(rho, jx, jy, n, flags, 3, (1e-4, 0), 1)
+    assert abs(r[fluid].sum() - rho[fluid].sum()) / rho[fluid].sum() < 8 * EPS * n
+
+
+# ----------------------------------------------------------------- P8 north-wall worked example
+def _read_north_wall():
+    terms = []
+    with open(os.path.join(GOLDEN, "north_wall.txt")) as fh:
+        for line in fh:
+            line = line.split("#")[0].strip()
+            if line:
+                kind, dx, dy, k = line.split()[:4]
+                terms.append((kind, int(dx), int(dy), int(k)))
+    return terms
+
+
+@pytest.mark.parametrize("F", [(0.0, 0.0), (1e-3, 2e-3)])
+def test_p8_north_wall_worked_example(F):
+    terms = _read_north_wall()
+    assert len(terms) == 9
+    rng = _rng(9)
+    ny, nx = 4, 5
+    flags = np.zeros((ny, nx), np.uint8)
+    flags[3, :] = oracle.SOLID          # the north wall
+    flags[0, :] = oracle.SOLID
+    rho, jx, jy = _random_state(rng, ny, nx, 5e-2, 5e-2)
+    X, Y = 2, 2
+    r, u, v = oracle.step(rho, jx, jy, flags, 1, F, 0)
+
+    def q(x):
+        return Fraction(float(x))
+
+    def feq(k, j, i):
+        rr = q(rho[j, i])
+        ux = (q(jx[j, i]) + q(F[0])) / rr
+        uy = (q(jy[j, i]) + q(F[1])) / rr
+        eu = bgk.EX[k] * ux + bgk.EY[k] * uy
+        w = Fraction(bgk.W[k]).limit_denominator(100)
+        return w * rr * (1 - Fraction(3, 2) * (ux * ux + uy * uy) + 3 * eu + Fraction(9, 2) * eu * eu)
+
+    R = Jx = Jy = Fraction(0)
+    for kind, dx, dy, k in terms:
+        if kind == "wall":
+            val = Fraction(bgk.W[k]).limit_denominator(100) * q(rho[Y, X])
+            arrive = bgk.opposite(k)
+        else:
+            val = feq(k, Y + dy, X + dx)
+            arrive = k
+        R += val
+        Jx += bgk.EX[arrive] * val
+        Jy += bgk.EY[arrive] * val
+    assert r[Y, X] == pytest.approx(float(R), rel=1e-15, abs=1e-15)
+    assert u[Y, X] == pytest.approx(float(Jx), abs=1e-15)
+    assert v[Y, X] == pytest.approx(float(Jy), abs=1e-15)
+
+
+# ----------------------------------------------------------------- P9 memory formulas
+def test_p9_memory_example_of_the_paper():
+    vals = {}
+    with open(os.path.join(GOLDEN, "memory_example.txt")) as fh:
+        for line in fh:
+            line = line.split("#")[0].strip()
+            if line:
+                key, val = line.split()
+                vals[key] = float(val)
+    n = int(vals["nodes"])
+    assert cf.memory_standard(9, 3, 4) == 21 * 4
+    assert cf.memory_lbmtau1(3, 4) == 6 * 4
+    assert n * cf.memory_standard(9, 3, 4) == vals["bytes_standard"]
+    assert n * cf.memory_lbmtau1(3, 4) == vals["bytes_lbmtau1"]
+    assert 1 - cf.memory_lbmtau1(3, 4) / cf.memory_standard(9, 3, 4) == pytest.approx(
+        vals["saving_d2q9_from_counts"], rel=1e-15)
+    # D3Q27: N_f = 4
+    assert 1 - cf.memory_lbmtau1(4, 4) / cf.memory_standard(27, 4, 4) == pytest.approx(
+        vals["saving_d3q27_approx"], abs=0.005)
+
+
+# ----------------------------------------------------------------- reductions
+def test_reduce_definitions():
+    rng = _rng(11)
+    ny, nx = 9, 8
+    flags = (rng.random((ny, nx)) < 0.3).astype(np.uint8)
+    rho, jx, jy = _random_state(rng, ny, nx)
+    snap = _random_state(rng, ny, nx)
+    d = oracle.reduce(rho, jx, jy, flags, snap)
+    fl = flags == 0
+    assert d["fluid"] == fl.sum()
+    assert d["mass"] == pytest.approx(rho[fl].sum(), rel=1e-15)
+    assert d["mom_x"] == pytest.approx(jx[fl].sum(), rel=1e-14)
+    du = np.abs(jx / rho - snap[1] / snap[0])[fl].max()
+    dv = np.abs(jy / rho - snap[2] / snap[0])[fl].max()
+    assert d["residual"] == max(du, dv)
+    rho2 = rho.copy()
+    rho2[np.argwhere(fl)[0][0], np.argwhere(fl)[0][1]] = np.nan
+    assert oracle.reduce(rho2, jx, jy, flags)["nonfinite"] == 1
+
+
+def test_lid_cavity_mass_is_not_conserved_but_fixed_row_is_held():
+    """The lid (FIXED row, Appendix A) is a density reservoir and is never updated."""
+    ny = nx = 12
+    flags = _cavity_flags(ny, nx, obstacle=False)
+    rho = np.ones((ny, nx))
+    jx = np.zeros((ny, nx))
+    jx[-1, 1:-1] = 0.1
+    r, u, v = oracle.run(rho, jx, np.zeros((ny, nx)), 200, flags, 0, (0, 0), 0)
+    assert np.array_equal(u[-1], jx[-1]) and np.array_equal(r[-1], rho[-1])
+    assert u[-2, nx // 2] > 0.01        # the lid drags the top fluid row along
