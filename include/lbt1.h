@@ -1,0 +1,245 @@
+/*
+ * lbt1.h -- C ABI of the MI355X LBMTau1 D2Q9 library (liblbt1.so).
+ *
+ * Method: M. Matyka and M. Dzikowski, "Memory-efficient Lattice Boltzmann
+ * Method for low Reynolds number flows" (arXiv:1912.09327).  With the BGK
+ * relaxation time fixed at tau = 1 (Eq. LBMTau1) every post-collision
+ * population equals its equilibrium (Eq. maxwellboltzmann), so a node keeps
+ * only its density and momentum, and one time step rebuilds the equilibria
+ * of the nine upwind neighbours and sums them (Eq. rhotau1, Eq. utau1 read
+ * as momentum sums, Algorithm 1).
+ *
+ * The calls follow the paper's statement of the problem (Algorithm 1 and
+ * Appendix A): declare fields and flags (lbt1_create_grid), initialise them
+ * (lbt1_set_geometry, the algorithm's initialisation), repeat the step
+ * (lbt1_step), read density and momentum back (lbt1_read_moments, the
+ * algorithm's optional visualisation).  lbt1_reduce adds the steady-state
+ * diagnostics of section 3 (velocity change between two times, mass).
+ * The lbt1_batch_* calls run many independent grids together.
+ *
+ * Conventions for every call:
+ *   - all calls return lbt1_status; nothing throws, aborts or exits across
+ *     the ABI; on a non-OK status lbt1_last_error() gives a message for the
+ *     calling thread.
+ *   - host arrays are caller-owned, [ny][nx] row-major with x fastest, and
+ *     are only read or written during the call.
+ *   - handles are owned by the library until the matching destroy call.  A
+ *     handle is not thread-safe; distinct handles may be used from distinct
+ *     threads.
+ *   - device work is asynchronous with respect to the host unless a call
+ *     says it synchronises.
+ *   - nothing on this path falls back to the CPU: without a usable gfx950
+ *     device, calls that need one return LBT1_EDEVICE.
+ */
+#ifndef LBT1_H
+#define LBT1_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbt1_grid lbt1_grid;   /* opaque; one 2-D lattice and its device state */
+typedef struct lbt1_batch lbt1_batch; /* opaque; a set of resident grids stepped together */
+
+typedef enum {
+  LBT1_OK = 0,
+  LBT1_EINVAL = 1,     /* bad argument (sizes, flags, densities, handle) */
+  LBT1_ENOMEM = 2,     /* device or host allocation failed, or caller buffer too small */
+  LBT1_EDEVICE = 3,    /* a HIP call failed or no gfx950 device is usable */
+  LBT1_ESTATE = 4,     /* call out of order (e.g. lbt1_step before lbt1_set_geometry) */
+  LBT1_EBUSY = 5,      /* batch has no free slot or HBM budget for the grid */
+  LBT1_ENONFINITE = 6  /* a grid's moments became non-finite (reported by poll) */
+} lbt1_status;
+
+/* Storage of the moment planes.  Every variant stores the density as the
+ * deviation rho - 1 and the momentum j = (jx, jy) (the "shifted" form);
+ * F64 computes in double, the others in float. */
+typedef enum {
+  LBT1_F64 = 0,  /* 8 bytes per value */
+  LBT1_F32 = 1,  /* 4 bytes per value */
+  LBT1_F16S = 2, /* IEEE binary16, round-to-nearest-even, optional power-of-two scale */
+  LBT1_BF16S = 3 /* bfloat16, round-to-nearest-even, optional power-of-two scale */
+} lbt1_precision;
+
+/* Treatment of a link from a fluid node x to a solid neighbour x + e_k. */
+typedef enum {
+  LBT1_WALL_PAPER = 0,  /* Eq. feqnoslip: the term is w_k * rho(x), the zero-velocity
+                           equilibrium of x itself (the paper's rule, default) */
+  LBT1_WALL_HALFWAY = 1 /* half-way bounce-back: the equilibrium x sends toward the
+                           wall, f^eq_k(rho(x), u(x)), returns reversed */
+} lbt1_wall;
+
+/* Node flags (uint8 values of the flag plane). */
+enum {
+  LBT1_FLUID = 0, /* updated every step */
+  LBT1_SOLID = 1, /* no-slip wall node; never updated, never a source */
+  LBT1_FIXED = 2  /* Dirichlet node (the moving lid of Appendix A): a source with its
+                     stored moments, never updated */
+};
+
+enum { LBT1_PERIODIC_X = 1u, LBT1_PERIODIC_Y = 2u };
+
+/* lbt1_grid_desc.options bits */
+enum { LBT1_OPT_SNAPSHOT = 1u /* keep a copy of the state for the residual */ };
+
+/* lbt1_reduce what-mask bits and output slots */
+enum {
+  LBT1_REDUCE_MASS = 1u,      /* out[0] = sum of rho over FLUID nodes */
+  LBT1_REDUCE_MOMENTUM = 2u,  /* out[1], out[2] = sum of jx, jy over FLUID nodes */
+  LBT1_REDUCE_RESIDUAL = 4u,  /* out[3] = max over FLUID nodes and both components of
+                                 |u - u_snap|, u = j / rho, against the snapshot taken
+                                 by the previous residual call (or lbt1_set_geometry);
+                                 the snapshot is then refreshed to the current state */
+  LBT1_REDUCE_NONFINITE = 8u  /* out[4] = number of FLUID nodes with a non-finite value */
+};
+#define LBT1_REDUCE_SLOTS 6 /* out[5] = number of FLUID nodes (always written) */
+
+typedef struct {
+  int32_t nx, ny;        /* lattice size, each >= 3 and <= 65536 */
+  uint32_t periodic;     /* LBT1_PERIODIC_X | LBT1_PERIODIC_Y; a neighbour outside a
+                            non-periodic axis counts as SOLID */
+  int32_t prec;          /* lbt1_precision */
+  int32_t wall;          /* lbt1_wall */
+  uint32_t options;      /* LBT1_OPT_* */
+  double force[2];       /* body force F, added to the momentum before the equilibrium
+                            velocity (j + F) / rho is formed (Algorithm 1); uniform */
+  double scale[2];       /* F16S/BF16S: stored value = value / scale, for rho - 1 and for
+                            j; must be powers of two; 0 means 1 */
+  void *device_buffer;   /* optional caller-owned device memory of at least
+                            lbt1_grid_bytes(...) bytes, 256-byte aligned; NULL: the
+                            library allocates */
+  size_t device_bytes;   /* size of device_buffer */
+  void *stream;          /* hipStream_t to run on; NULL: a library-owned stream */
+} lbt1_grid_desc;
+
+/* Device bytes a grid of this shape needs: two parities of three moment
+ * planes (the paper's 2 N_f c per node, Eq. LBMTau1memory, with rows padded
+ * to 64 values), one flag byte per node, three more planes with
+ * LBT1_OPT_SNAPSHOT, and a small reduction workspace.  0 on bad arguments. */
+size_t lbt1_grid_bytes(int32_t nx, int32_t ny, int32_t prec, uint32_t options);
+
+/* Create a grid (no device work yet besides allocation).  *out receives the handle. */
+lbt1_status lbt1_create_grid(const lbt1_grid_desc *desc, lbt1_grid **out);
+
+/* Initialise flags and moments in both parities (the algorithm's first line).
+ *   flags: ny*nx uint8 in {FLUID, SOLID, FIXED}, or NULL for all FLUID
+ *   rho, jx, jy: ny*nx doubles each, or all three NULL for rho = 1, j = 0;
+ *                rho must be finite and > 0, j finite.
+ * Synchronises the grid's stream.  EINVAL on bad values. */
+lbt1_status lbt1_set_geometry(lbt1_grid *g, const uint8_t *flags, const double *rho,
+                              const double *jx, const double *jy);
+
+/* Enqueue n >= 0 LBMTau1 steps (Algorithm 1) on the grid's stream and return.
+ * ESTATE before lbt1_set_geometry. */
+lbt1_status lbt1_step(lbt1_grid *g, int64_t n);
+
+/* Copy the current density rho and momentum (jx, jy) into ny*nx host arrays
+ * (any of them may be NULL).  Synchronises the grid's stream. */
+lbt1_status lbt1_read_moments(lbt1_grid *g, double *rho, double *jx, double *jy);
+
+/* FP64 diagnostics over FLUID nodes, see LBT1_REDUCE_*; out has
+ * LBT1_REDUCE_SLOTS doubles, slots not asked for are left untouched except
+ * out[5].  Synchronises the grid's stream. */
+lbt1_status lbt1_reduce(lbt1_grid *g, uint32_t what, double *out);
+
+/* Wait until all work enqueued on the grid's stream has finished. */
+lbt1_status lbt1_sync(lbt1_grid *g);
+
+/* Release the grid (after its stream drained).  NULL is accepted. */
+lbt1_status lbt1_destroy_grid(lbt1_grid *g);
+
+/* Message for the last non-OK status returned to this thread ("" if none). */
+const char *lbt1_last_error(void);
+
+/* ---------------------------------------------------------------- kernel choice */
+
+/* Step kernel families. */
+enum {
+  LBT1_KERNEL_AUTO = 0,   /* library choice (tuned table, else heuristic) */
+  LBT1_KERNEL_GATHER = 1, /* one thread per node, nine neighbour reads */
+  LBT1_KERNEL_STRIP = 2   /* a wavefront walks a strip of rows; each lane owns `vec`
+                             adjacent columns, neighbour columns come from adjacent
+                             lanes; every moment is read from memory once per strip */
+};
+
+typedef struct {
+  int32_t kernel; /* LBT1_KERNEL_* */
+  int32_t vec;    /* STRIP: columns per lane, 1, 2, 4 or 8 (must divide nx) */
+  int32_t rows;   /* STRIP: rows per strip, 6, 14 or 30 */
+  int32_t waves;  /* STRIP: resident wavefronts per CU the launch aims at (1..32);
+                     0 = one wavefront per strip, no grid-stride loop */
+} lbt1_kernel_config;
+
+/* Select the step kernel for a grid.  EINVAL if the combination is not built
+ * or does not fit the grid. */
+lbt1_status lbt1_set_kernel(lbt1_grid *g, const lbt1_kernel_config *cfg);
+
+/* The configuration lbt1_step uses now; name (optional) receives the kernel's
+ * symbol-like name, NUL-terminated, at most name_cap bytes. */
+lbt1_status lbt1_get_kernel(lbt1_grid *g, lbt1_kernel_config *cfg, char *name, size_t name_cap);
+
+/* Time every built configuration that fits this grid on a scratch copy of it
+ * (`steps` steps each, best of `reps`), select the fastest and return it in
+ * *best (optional) and its time per step in *ms_per_step (optional).  The
+ * grid's state is unchanged.  The result is remembered for grids of the same
+ * precision, flag use and size in this process. */
+lbt1_status lbt1_autotune(lbt1_grid *g, int32_t steps, int32_t reps, lbt1_kernel_config *best,
+                          double *ms_per_step);
+
+/* ---------------------------------------------------------------- batches */
+
+/* A batch steps every resident grid together: one launch per time step covers
+ * the strips of all grids, and bursts of steps run as a HIP graph.
+ *   hbm_budget_bytes: admission limit on the sum of lbt1_grid_bytes of resident grids
+ *   max_slots:        admission limit on the number of resident grids (1..65536)
+ *   stream:           hipStream_t for the batch's work, NULL for a library stream
+ * Grids admitted must be F16S/BF16S/F32/F64 grids created with LBT1_OPT_SNAPSHOT, whose
+ * geometry is set, on the same device; all grids of a batch share one precision. */
+lbt1_status lbt1_batch_create(size_t hbm_budget_bytes, int32_t max_slots, void *stream,
+                              lbt1_batch **out);
+
+/* Make g resident.  It will take at most step_budget more steps and is
+ * finished early when its residual (LBT1_REDUCE_RESIDUAL, checked at burst
+ * ends) is <= residual_tol (use a negative value to disable).  *slot receives
+ * its slot id.  EBUSY when the budget or slots are exhausted (nothing changes).
+ * The grid must not be stepped or destroyed while resident. */
+lbt1_status lbt1_batch_admit(lbt1_batch *b, lbt1_grid *g, int64_t step_budget, double residual_tol,
+                             int32_t *slot);
+
+/* Run one burst of burst_steps steps (>= 1) for every resident, unfinished grid,
+ * then the residual / non-finite check of every such grid.  Synchronises. */
+lbt1_status lbt1_batch_run(lbt1_batch *b, int32_t burst_steps);
+
+/* Report the slots that are finished (budget used, converged or non-finite):
+ * up to cap slot ids go to done_slots, their count to *n_done.  The reason is
+ * given by lbt1_batch_slot_info.  Finished grids stay resident (and are not
+ * stepped) until evicted. */
+lbt1_status lbt1_batch_poll(lbt1_batch *b, int32_t *done_slots, int32_t cap, int32_t *n_done);
+
+/* Reason codes of lbt1_batch_slot_info */
+enum {
+  LBT1_SLOT_FREE = 0,
+  LBT1_SLOT_RUNNING = 1,
+  LBT1_SLOT_BUDGET = 2,    /* finished: step budget used */
+  LBT1_SLOT_CONVERGED = 3, /* finished: residual <= tolerance */
+  LBT1_SLOT_NONFINITE = 4  /* finished: non-finite moments (the grid is not stepped further) */
+};
+
+/* State of a slot: reason (LBT1_SLOT_*), steps taken since admission, last residual. */
+lbt1_status lbt1_batch_slot_info(lbt1_batch *b, int32_t slot, int32_t *state, int64_t *steps,
+                                 double *residual);
+
+/* Remove the grid in `slot` from the batch (it stays valid and owned by the caller). */
+lbt1_status lbt1_batch_evict(lbt1_batch *b, int32_t slot);
+
+/* Release the batch (it must be empty or its grids are simply evicted). */
+lbt1_status lbt1_batch_destroy(lbt1_batch *b);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBT1_H */

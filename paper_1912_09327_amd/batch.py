@@ -1,0 +1,67 @@
+"""Python handle for a batch of resident grids (lbt1_batch_* of the C ABI)."""
+import ctypes
+
+from . import _capi as C
+from .grid import default_stream
+
+
+class Batch:
+    """Resident grids stepped together in HIP-graph bursts.
+
+    ``admit`` returns a slot id, or ``None`` when the HBM budget or the slots
+    are exhausted (the library's EBUSY).
+    """
+
+    def __init__(self, hbm_budget_bytes, max_slots, stream=None):
+        self.stream = stream if stream is not None else default_stream()
+        h = ctypes.c_void_p()
+        C.check(C.lib.lbt1_batch_create(int(hbm_budget_bytes), int(max_slots), self.stream.cuda_stream,
+                                        ctypes.byref(h)))
+        self.handle = h
+        self.grids = {}
+
+    def admit(self, grid, step_budget, residual_tol=-1.0):
+        slot = ctypes.c_int32()
+        st = C.lib.lbt1_batch_admit(self.handle, grid.handle, int(step_budget), float(residual_tol),
+                                    ctypes.byref(slot))
+        if st == C.EBUSY:
+            return None
+        C.check(st)
+        self.grids[slot.value] = grid
+        return slot.value
+
+    def run(self, burst_steps):
+        C.check(C.lib.lbt1_batch_run(self.handle, int(burst_steps)))
+
+    def poll(self):
+        cap = max(1, len(self.grids))
+        buf = (ctypes.c_int32 * cap)()
+        n = ctypes.c_int32()
+        C.check(C.lib.lbt1_batch_poll(self.handle, buf, cap, ctypes.byref(n)))
+        return [buf[i] for i in range(min(n.value, cap))]
+
+    def slot_info(self, slot):
+        st = ctypes.c_int32()
+        steps = ctypes.c_int64()
+        res = ctypes.c_double()
+        C.check(C.lib.lbt1_batch_slot_info(self.handle, int(slot), ctypes.byref(st), ctypes.byref(steps),
+                                           ctypes.byref(res)))
+        return st.value, steps.value, res.value
+
+    def evict(self, slot):
+        C.check(C.lib.lbt1_batch_evict(self.handle, int(slot)))
+        return self.grids.pop(slot)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            C.check(C.lib.lbt1_batch_destroy(self.handle))
+            self.handle = None
+            self.grids = {}
+
+    def __del__(self):
+        try:
+            if getattr(self, "handle", None):
+                C.lib.lbt1_batch_destroy(self.handle)
+                self.handle = None
+        except Exception:
+            pass

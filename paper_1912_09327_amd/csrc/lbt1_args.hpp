@@ -1,0 +1,59 @@
+// Kernel argument structures shared by the kernels and the host runtime.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lbt1_device.hpp"
+
+namespace lbt1 {
+
+struct StripMap {
+  int strips_x, strips_y;  // strips per row band / per column band
+  int units;               // groups of 4 vertically adjacent strips (one per block)
+  int per_xcd;             // units per XCD range
+  int persistent;          // 0: one block per unit; else grid-stride within the XCD range
+};
+
+struct ReduceArgs {
+  const void *cur[3];
+  void *snap[3];
+  const uint8_t *flags;  // NULL: every node FLUID
+  int nx, ny, pitch;
+  double sc_d, sc_j;
+  uint32_t what;         // LBT1_REDUCE_* bits
+  double *partials;      // 6 per block
+};
+
+// Descriptor of one resident grid (device copy refreshed by the host before
+// every burst).  parity0 is the grid's parity at the start of the burst;
+// the grid takes steps_left (<= burst length) steps in this burst.
+struct BatchGrid {
+  void *plane[2][3];
+  const uint8_t *flags;
+  int nx, ny, pitch;
+  uint32_t periodic;
+  int wall;
+  int parity0;
+  int steps_left;
+  int strips_y;
+  double fx, fy, sc_d, sc_j, is_d, is_j;
+};
+
+struct BatchStepArgs {
+  const BatchGrid *grids;
+  const int2 *items;  // (slot, strip index), strips ordered down each column band
+  const int *count;   // number of items (device memory, so a graph need not change)
+  int step;           // step index inside the burst
+};
+
+// Per-grid diagnostics after a burst: one block per active grid, the six
+// slots of k_reduce_partial, snapshot refreshed.  out[slot * 6 + q].
+struct BatchReduceArgs {
+  const BatchGrid *grids;
+  void *const *snaps;  // 3 per slot
+  const int *active;   // slots to reduce
+  const int *nactive;
+  double *out;
+};
+
+}  // namespace lbt1

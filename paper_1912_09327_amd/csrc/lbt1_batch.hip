@@ -1,0 +1,421 @@
+// Batched stepping of many resident grids (lbt1_batch_* of include/lbt1.h).
+//
+// Every resident grid is cut into strips (64*vec columns by 14 rows); the
+// strips of all grids with the same columns-per-lane class form one work
+// list, and one launch per class and time step covers the whole list, so a
+// step of hundreds of small, uneven grids costs a handful of launches.  A
+// burst of K steps plus the per-grid residual check is one HIP graph; the
+// grid descriptors and work lists live in device memory, so admitting or
+// finishing grids changes data, not the graph (it is rebuilt only when the
+// burst length or the set of non-empty classes changes, or a list outgrows
+// its allocation).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/lbt1.h"
+#include "lbt1_internal.hpp"
+#include "lbt1_runtime.hpp"
+
+namespace lbt1 {
+
+struct Slot {
+  lbt1_grid *g = nullptr;
+  int64_t budget = 0, taken = 0;
+  double tol = -1.0, residual = -1.0;
+  int state = LBT1_SLOT_FREE;
+  size_t bytes = 0;
+  int vclass = 0;
+  int steps_this_burst = 0;
+};
+
+}  // namespace lbt1
+
+struct lbt1_batch {
+  int device = 0, cus = 0;
+  size_t budget = 0, used = 0;
+  int max_slots = 0;
+  int prec = -1;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::vector<lbt1::Slot> slots;
+  // device side
+  lbt1::BatchGrid *d_grids = nullptr;
+  void **d_snaps = nullptr;
+  int *d_active = nullptr;
+  int *d_counts = nullptr;  // [4] item counts, [4] active count
+  double *d_red = nullptr;
+  int2 *d_items[4] = {nullptr, nullptr, nullptr, nullptr};
+  size_t item_cap[4] = {0, 0, 0, 0};
+  // pinned host mirrors
+  lbt1::BatchGrid *h_grids = nullptr;
+  void **h_snaps = nullptr;
+  int *h_active = nullptr;
+  int *h_counts = nullptr;
+  double *h_red = nullptr;
+  std::vector<int2> items[4];
+  bool items_dirty = true;
+  hipGraphExec_t graph = nullptr;
+  int graph_K = 0, graph_mask = -1;
+  bool graph_valid = false;
+};
+
+namespace lbt1 {
+
+static const int kVecOfClass[4] = {1, 2, 4, 8};
+
+static int vec_class_for(int prec, int nx) {
+  const int maxc = prec == LBT1_F64 ? 1 : prec == LBT1_F32 ? 2 : 3;
+  for (int c = maxc; c >= 0; --c) {
+    const int v = kVecOfClass[c];
+    if (nx % v == 0 && 64 * v <= std::max(64, nx)) return c;
+  }
+  return 0;
+}
+
+static void rebuild_items(lbt1_batch *b) {
+  for (int c = 0; c < 4; ++c) b->items[c].clear();
+  for (int s = 0; s < b->max_slots; ++s) {
+    const Slot &sl = b->slots[s];
+    if (sl.state == LBT1_SLOT_FREE) continue;
+    const int v = kVecOfClass[sl.vclass];
+    const int sx = (sl.g->nx + 64 * v - 1) / (64 * v);
+    const int sy = (sl.g->ny + 13) / 14;
+    for (int k = 0; k < sx * sy; ++k) b->items[sl.vclass].push_back(make_int2(s, k));
+  }
+}
+
+static lbt1_status upload_items(lbt1_batch *b) {
+  hipError_t e;
+  for (int c = 0; c < 4; ++c) {
+    const size_t n = b->items[c].size();
+    if (n > b->item_cap[c]) {
+      size_t cap = std::max<size_t>(1024, b->item_cap[c]);
+      while (cap < n) cap *= 2;
+      if (b->d_items[c]) (void)hipFree(b->d_items[c]);
+      b->d_items[c] = nullptr;
+      b->item_cap[c] = 0;
+      if ((e = hipMalloc(&b->d_items[c], cap * sizeof(int2))) != hipSuccess) return hip_fail(e, "hipMalloc items");
+      b->item_cap[c] = cap;
+      b->graph_valid = false;  // kernel arguments point at the old list
+    }
+    if (n && (e = hipMemcpyAsync(b->d_items[c], b->items[c].data(), n * sizeof(int2), hipMemcpyHostToDevice, b->stream)) !=
+                 hipSuccess)
+      return hip_fail(e, "items H2D");
+    b->h_counts[c] = (int)n;
+  }
+  b->items_dirty = false;
+  return LBT1_OK;
+}
+
+static lbt1_status build_graph(lbt1_batch *b, int K, int mask) {
+  hipError_t e;
+  hipGraph_t graph = nullptr;
+  if ((e = hipGraphCreate(&graph, 0)) != hipSuccess) return hip_fail(e, "hipGraphCreate");
+  hipGraphNode_t prev = nullptr;
+  const int blocks = std::max(8, b->cus * 2);  // 8 wavefronts per CU
+  std::vector<BatchStepArgs> argv;
+  argv.reserve((size_t)K * 4);
+  auto add = [&](const void *fn, dim3 grid, dim3 block, void **args) -> lbt1_status {
+    hipKernelNodeParams kp{};
+    kp.func = const_cast<void *>(fn);
+    kp.gridDim = grid;
+    kp.blockDim = block;
+    kp.kernelParams = args;
+    hipGraphNode_t node;
+    hipError_t err = hipGraphAddKernelNode(&node, graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
+    if (err != hipSuccess) return hip_fail(err, "hipGraphAddKernelNode");
+    prev = node;
+    return LBT1_OK;
+  };
+  lbt1_status st = LBT1_OK;
+  for (int s = 0; s < K && !st; ++s) {
+    for (int c = 0; c < 4 && !st; ++c) {
+      if (!(mask & (1 << c))) continue;
+      BatchStepArgs a;
+      a.grids = b->d_grids;
+      a.items = b->d_items[c];
+      a.count = b->d_counts + c;
+      a.step = s;
+      argv.push_back(a);
+      void *args[] = {&argv.back()};
+      st = add(batch_step_kernel(b->prec, c), dim3(blocks), dim3(256), args);
+    }
+  }
+  BatchReduceArgs ra;
+  ra.grids = b->d_grids;
+  ra.snaps = b->d_snaps;
+  ra.active = b->d_active;
+  ra.nactive = b->d_counts + 4;
+  ra.out = b->d_red;
+  if (!st) {
+    void *args[] = {&ra};
+    st = add(batch_reduce_kernel(b->prec), dim3(std::max(8, b->cus * 2)), dim3(256), args);
+  }
+  if (st) {
+    (void)hipGraphDestroy(graph);
+    return st;
+  }
+  if (b->graph) (void)hipGraphExecDestroy(b->graph);
+  b->graph = nullptr;
+  e = hipGraphInstantiate(&b->graph, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+  b->graph_K = K;
+  b->graph_mask = mask;
+  b->graph_valid = true;
+  return LBT1_OK;
+}
+
+}  // namespace lbt1
+
+using namespace lbt1;
+
+extern "C" {
+
+lbt1_status lbt1_batch_create(size_t hbm_budget_bytes, int32_t max_slots, void *stream, lbt1_batch **out) {
+  clear_error();
+  if (!out) return fail(LBT1_EINVAL, "null argument");
+  *out = nullptr;
+  if (max_slots < 1 || max_slots > 65536) return fail(LBT1_EINVAL, "max_slots %d out of 1..65536", max_slots);
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return fail(LBT1_EDEVICE, "no HIP device is visible");
+  lbt1_batch *b = new (std::nothrow) lbt1_batch();
+  if (!b) return fail(LBT1_ENOMEM, "host allocation");
+  hipError_t e;
+  hipDeviceProp_t prop;
+  if ((e = hipGetDevice(&b->device)) != hipSuccess || (e = hipGetDeviceProperties(&prop, b->device)) != hipSuccess) {
+    delete b;
+    return hip_fail(e, "device query");
+  }
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+    delete b;
+    return fail(LBT1_EDEVICE, "device is %s; this library is built for gfx950", prop.gcnArchName);
+  }
+  b->cus = prop.multiProcessorCount;
+  b->budget = hbm_budget_bytes;
+  b->max_slots = max_slots;
+  b->slots.resize(max_slots);
+  const size_t ns = (size_t)max_slots;
+  bool ok = hipMalloc(&b->d_grids, ns * sizeof(BatchGrid)) == hipSuccess &&
+            hipMalloc(&b->d_snaps, ns * 3 * sizeof(void *)) == hipSuccess &&
+            hipMalloc(&b->d_active, ns * sizeof(int)) == hipSuccess &&
+            hipMalloc(&b->d_counts, 8 * sizeof(int)) == hipSuccess &&
+            hipMalloc(&b->d_red, ns * 6 * sizeof(double)) == hipSuccess &&
+            hipHostMalloc((void **)&b->h_grids, ns * sizeof(BatchGrid), hipHostMallocDefault) == hipSuccess &&
+            hipHostMalloc((void **)&b->h_snaps, ns * 3 * sizeof(void *), hipHostMallocDefault) == hipSuccess &&
+            hipHostMalloc((void **)&b->h_active, ns * sizeof(int), hipHostMallocDefault) == hipSuccess &&
+            hipHostMalloc((void **)&b->h_counts, 8 * sizeof(int), hipHostMallocDefault) == hipSuccess &&
+            hipHostMalloc((void **)&b->h_red, ns * 6 * sizeof(double), hipHostMallocDefault) == hipSuccess;
+  if (ok && stream) {
+    b->stream = (hipStream_t)stream;
+  } else if (ok) {
+    ok = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) == hipSuccess;
+    b->own_stream = ok;
+  }
+  if (!ok) {
+    lbt1_batch_destroy(b);
+    return fail(LBT1_ENOMEM, "batch allocation failed");
+  }
+  std::memset(b->h_grids, 0, ns * sizeof(BatchGrid));
+  std::memset(b->h_snaps, 0, ns * 3 * sizeof(void *));
+  std::memset(b->h_counts, 0, 8 * sizeof(int));
+  *out = b;
+  return LBT1_OK;
+}
+
+lbt1_status lbt1_batch_admit(lbt1_batch *b, lbt1_grid *g, int64_t step_budget, double residual_tol, int32_t *slot) {
+  clear_error();
+  if (!b || !g || !slot) return fail(LBT1_EINVAL, "null argument");
+  if (step_budget < 0) return fail(LBT1_EINVAL, "negative step budget");
+  if (g->batch) return fail(LBT1_ESTATE, "grid is already resident in a batch");
+  if (!g->geometry) return fail(LBT1_ESTATE, "grid geometry is not set");
+  if (!g->snap[0]) return fail(LBT1_EINVAL, "batched grids need LBT1_OPT_SNAPSHOT");
+  if (g->device != b->device) return fail(LBT1_EINVAL, "grid is on another device");
+  if (b->prec >= 0 && g->prec != b->prec) return fail(LBT1_EINVAL, "batch precision is %d, grid has %d", b->prec, g->prec);
+  const size_t bytes = g->L.total;
+  if (b->used + bytes > b->budget) return fail(LBT1_EBUSY, "HBM budget: %zu used + %zu > %zu", b->used, bytes, b->budget);
+  int s = -1;
+  for (int i = 0; i < b->max_slots; ++i)
+    if (b->slots[i].state == LBT1_SLOT_FREE) {
+      s = i;
+      break;
+    }
+  if (s < 0) return fail(LBT1_EBUSY, "no free slot (%d in use)", b->max_slots);
+  // make sure the grid's own queued work is done before the batch stream touches it
+  hipError_t e;
+  if ((e = hipStreamSynchronize(g->stream)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  Slot &sl = b->slots[s];
+  sl = Slot();
+  sl.g = g;
+  sl.budget = step_budget;
+  sl.tol = residual_tol;
+  sl.state = step_budget > 0 ? LBT1_SLOT_RUNNING : LBT1_SLOT_BUDGET;
+  sl.bytes = bytes;
+  sl.vclass = vec_class_for(g->prec, g->nx);
+  b->prec = g->prec;
+  b->used += bytes;
+  g->batch = b;
+  g->slot = s;
+  BatchGrid &d = b->h_grids[s];
+  for (int p = 0; p < 2; ++p)
+    for (int q = 0; q < 3; ++q) d.plane[p][q] = g->plane[p][q];
+  d.flags = g->flags;
+  d.nx = g->nx;
+  d.ny = g->ny;
+  d.pitch = g->L.pitch;
+  d.periodic = g->periodic;
+  d.wall = g->wall;
+  d.parity0 = g->parity;
+  d.steps_left = 0;
+  d.strips_y = (g->ny + 13) / 14;
+  d.fx = g->F[0];
+  d.fy = g->F[1];
+  d.sc_d = g->sc[0];
+  d.sc_j = g->sc[1];
+  d.is_d = 1.0 / g->sc[0];
+  d.is_j = 1.0 / g->sc[1];
+  for (int q = 0; q < 3; ++q) b->h_snaps[3 * s + q] = g->snap[q];
+  b->items_dirty = true;
+  *slot = s;
+  return LBT1_OK;
+}
+
+lbt1_status lbt1_batch_run(lbt1_batch *b, int32_t burst_steps) {
+  clear_error();
+  if (!b) return fail(LBT1_EINVAL, "null batch");
+  if (burst_steps < 1 || burst_steps > 100000) return fail(LBT1_EINVAL, "burst_steps %d out of 1..100000", burst_steps);
+  hipError_t e;
+  if ((e = hipSetDevice(b->device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
+  int nact = 0;
+  for (int s = 0; s < b->max_slots; ++s) {
+    Slot &sl = b->slots[s];
+    BatchGrid &d = b->h_grids[s];
+    sl.steps_this_burst = 0;
+    d.steps_left = 0;
+    if (sl.state != LBT1_SLOT_RUNNING) continue;
+    const int64_t left = sl.budget - sl.taken;
+    sl.steps_this_burst = (int)std::min<int64_t>(burst_steps, left);
+    d.steps_left = sl.steps_this_burst;
+    d.parity0 = sl.g->parity;
+    b->h_active[nact++] = s;
+  }
+  if (nact == 0) return LBT1_OK;
+  b->h_counts[4] = nact;
+  if (b->items_dirty) {
+    rebuild_items(b);
+    lbt1_status st = upload_items(b);
+    if (st) return st;
+  }
+  int mask = 0;
+  for (int c = 0; c < 4; ++c)
+    if (!b->items[c].empty()) mask |= 1 << c;
+  const size_t ns = (size_t)b->max_slots;
+  if ((e = hipMemcpyAsync(b->d_grids, b->h_grids, ns * sizeof(BatchGrid), hipMemcpyHostToDevice, b->stream)) != hipSuccess ||
+      (e = hipMemcpyAsync(b->d_snaps, b->h_snaps, ns * 3 * sizeof(void *), hipMemcpyHostToDevice, b->stream)) != hipSuccess ||
+      (e = hipMemcpyAsync(b->d_active, b->h_active, (size_t)nact * sizeof(int), hipMemcpyHostToDevice, b->stream)) != hipSuccess ||
+      (e = hipMemcpyAsync(b->d_counts, b->h_counts, 8 * sizeof(int), hipMemcpyHostToDevice, b->stream)) != hipSuccess)
+    return hip_fail(e, "descriptor H2D");
+  if (!b->graph_valid || b->graph_K != burst_steps || b->graph_mask != mask) {
+    lbt1_status st = build_graph(b, burst_steps, mask);
+    if (st) return st;
+  }
+  if ((e = hipGraphLaunch(b->graph, b->stream)) != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+  if ((e = hipMemcpyAsync(b->h_red, b->d_red, ns * 6 * sizeof(double), hipMemcpyDeviceToHost, b->stream)) != hipSuccess)
+    return hip_fail(e, "results D2H");
+  if ((e = hipStreamSynchronize(b->stream)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  for (int k = 0; k < nact; ++k) {
+    const int s = b->h_active[k];
+    Slot &sl = b->slots[s];
+    const double *r = b->h_red + 6 * s;
+    sl.taken += sl.steps_this_burst;
+    sl.g->steps += sl.steps_this_burst;
+    sl.g->parity ^= sl.steps_this_burst & 1;
+    sl.residual = r[3];
+    if (r[4] > 0)
+      sl.state = LBT1_SLOT_NONFINITE;
+    else if (sl.tol >= 0 && sl.residual <= sl.tol)
+      sl.state = LBT1_SLOT_CONVERGED;
+    else if (sl.taken >= sl.budget)
+      sl.state = LBT1_SLOT_BUDGET;
+  }
+  return LBT1_OK;
+}
+
+lbt1_status lbt1_batch_poll(lbt1_batch *b, int32_t *done_slots, int32_t cap, int32_t *n_done) {
+  clear_error();
+  if (!b || !n_done || (cap > 0 && !done_slots)) return fail(LBT1_EINVAL, "null argument");
+  int n = 0;
+  for (int s = 0; s < b->max_slots; ++s) {
+    const int st = b->slots[s].state;
+    if (st == LBT1_SLOT_BUDGET || st == LBT1_SLOT_CONVERGED || st == LBT1_SLOT_NONFINITE) {
+      if (n < cap) done_slots[n] = s;
+      ++n;
+    }
+  }
+  *n_done = n;
+  return LBT1_OK;
+}
+
+lbt1_status lbt1_batch_slot_info(lbt1_batch *b, int32_t slot, int32_t *state, int64_t *steps, double *residual) {
+  clear_error();
+  if (!b) return fail(LBT1_EINVAL, "null batch");
+  if (slot < 0 || slot >= b->max_slots) return fail(LBT1_EINVAL, "slot %d out of range", slot);
+  const Slot &sl = b->slots[slot];
+  if (state) *state = sl.state;
+  if (steps) *steps = sl.taken;
+  if (residual) *residual = sl.residual;
+  return LBT1_OK;
+}
+
+lbt1_status lbt1_batch_evict(lbt1_batch *b, int32_t slot) {
+  clear_error();
+  if (!b) return fail(LBT1_EINVAL, "null batch");
+  if (slot < 0 || slot >= b->max_slots || b->slots[slot].state == LBT1_SLOT_FREE)
+    return fail(LBT1_EINVAL, "slot %d is not in use", slot);
+  hipError_t e;
+  if ((e = hipStreamSynchronize(b->stream)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  Slot &sl = b->slots[slot];
+  sl.g->batch = nullptr;
+  sl.g->slot = -1;
+  b->used -= sl.bytes;
+  sl = Slot();
+  std::memset(&b->h_grids[slot], 0, sizeof(BatchGrid));
+  b->items_dirty = true;
+  bool empty = true;
+  for (const auto &x : b->slots) empty &= x.state == LBT1_SLOT_FREE;
+  if (empty) b->prec = -1;
+  return LBT1_OK;
+}
+
+lbt1_status lbt1_batch_destroy(lbt1_batch *b) {
+  clear_error();
+  if (!b) return LBT1_OK;
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  for (auto &sl : b->slots)
+    if (sl.g) {
+      sl.g->batch = nullptr;
+      sl.g->slot = -1;
+    }
+  if (b->graph) (void)hipGraphExecDestroy(b->graph);
+  for (int c = 0; c < 4; ++c)
+    if (b->d_items[c]) (void)hipFree(b->d_items[c]);
+  if (b->d_grids) (void)hipFree(b->d_grids);
+  if (b->d_snaps) (void)hipFree(b->d_snaps);
+  if (b->d_active) (void)hipFree(b->d_active);
+  if (b->d_counts) (void)hipFree(b->d_counts);
+  if (b->d_red) (void)hipFree(b->d_red);
+  if (b->h_grids) (void)hipHostFree(b->h_grids);
+  if (b->h_snaps) (void)hipHostFree(b->h_snaps);
+  if (b->h_active) (void)hipHostFree(b->h_active);
+  if (b->h_counts) (void)hipHostFree(b->h_counts);
+  if (b->h_red) (void)hipHostFree(b->h_red);
+  if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+  delete b;
+  return LBT1_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,163 @@
+// Device-side arithmetic of the LBMTau1 D2Q9 step for gfx950.
+//
+// Method (arXiv:1912.09327): with tau = 1 the populations leaving a node are
+// its equilibria (Eq. LBMTau1), so the new density and momentum of a fluid
+// node x are the sums, over the nine directions q, of the equilibrium
+// f^eq_q of the upwind node x - e_q (Eq. rhotau1, Eq. utau1, Algorithm 1).
+// A link whose upwind node is a wall contributes w_q rho(x) (Eq. feqnoslip,
+// the paper's rule) or, under half-way bounce-back, the equilibrium x sent
+// toward the wall.
+//
+// Arithmetic form used by every kernel (so that all kernels agree bit for
+// bit): the density is carried as the deviation d = rho - 1, and
+// Eq. maxwellboltzmann is expanded in the momentum J = j + F (the force
+// shift of Algorithm 1) and the tensor P = J J / rho:
+//     f^eq_q - w_q = w_q [ d + 3 e_q.J + 4.5 (e_q.J)^2 / rho - 1.5 |J|^2 / rho ].
+// The constant parts w_q of the nine terms arriving at any node sum to one,
+// so the new deviation is the sum of the bracketed parts alone; the rounding
+// of reduced-precision arithmetic then scales with |d|, not with rho ~ 1.
+// One reciprocal per source node replaces the per-link divisions of the
+// paper's listing.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbt1 {
+
+enum : int { P_F64 = 0, P_F32 = 1, P_F16S = 2, P_BF16S = 3 };
+enum : uint8_t { NODE_FLUID = 0, NODE_SOLID = 1, NODE_FIXED = 2 };
+enum : int { WALL_PAPER = 0, WALL_HALFWAY = 1 };
+
+// ----------------------------------------------------------------- storage codecs
+template <int P> struct Traits;
+template <> struct Traits<P_F64> {
+  using S = double;  // stored value
+  using C = double;  // arithmetic
+  static constexpr bool kScaled = false;
+  __device__ static inline C dec(S s) { return s; }
+  __device__ static inline S enc(C c) { return c; }
+};
+template <> struct Traits<P_F32> {
+  using S = float;
+  using C = float;
+  static constexpr bool kScaled = false;
+  __device__ static inline C dec(S s) { return s; }
+  __device__ static inline S enc(C c) { return c; }
+};
+template <> struct Traits<P_F16S> {
+  using S = uint16_t;  // IEEE binary16 bits
+  using C = float;
+  static constexpr bool kScaled = true;
+  __device__ static inline C dec(S s) { return (float)__builtin_bit_cast(_Float16, s); }
+  // v_cvt_f16_f32: round to nearest even under the default mode
+  __device__ static inline S enc(C c) { return __builtin_bit_cast(uint16_t, (_Float16)c); }
+};
+template <> struct Traits<P_BF16S> {
+  using S = uint16_t;  // bfloat16 bits
+  using C = float;
+  static constexpr bool kScaled = true;
+  __device__ static inline C dec(S s) { return __builtin_bit_cast(float, (uint32_t)s << 16); }
+  // gfx950 v_cvt_pk_bf16_f32: round to nearest even
+  __device__ static inline S enc(C c) { return __builtin_bit_cast(uint16_t, (__bf16)c); }
+};
+
+template <typename C> __device__ inline C recip(C x);
+template <> __device__ inline float recip<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <> __device__ inline double recip<double>(double x) { return 1.0 / x; }
+
+template <typename C> __device__ inline C fmaC(C a, C b, C c);
+template <> __device__ inline float fmaC<float>(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+template <> __device__ inline double fmaC<double>(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// D2Q9 velocities in the paper's order (section 2) and their inverses.
+__device__ constexpr int kEx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+__device__ constexpr int kEy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+__device__ constexpr int kInv[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+
+// ----------------------------------------------------------------- emission
+// The nine equilibrium deviations a source node with deviation d and
+// momentum (jx, jy) sends out, f[q] travelling along e_q.
+template <typename C>
+__device__ __forceinline__ void emit(C d, C jx, C jy, C Fx, C Fy, C f[9]) {
+  const C Jx = jx + Fx;
+  const C Jy = jy + Fy;
+  const C inv = recip<C>(C(1) + d);
+  const C ux = Jx * inv;
+  const C uy = Jy * inv;
+  const C pxx = Jx * ux;
+  const C pyy = Jy * uy;
+  const C pxy = Jx * uy;
+  const C t = pxx + pyy;
+  f[0] = C(4.0 / 9.0) * fmaC<C>(C(-1.5), t, d);
+  // axes: w = 1/9, bracket d + 3 P_aa - 1.5 P_bb +- 3 J_a
+  const C bx = C(1.0 / 9.0) * fmaC<C>(C(3), pxx, fmaC<C>(C(-1.5), pyy, d));
+  const C by = C(1.0 / 9.0) * fmaC<C>(C(3), pyy, fmaC<C>(C(-1.5), pxx, d));
+  f[1] = fmaC<C>(C(1.0 / 3.0), Jx, bx);
+  f[3] = fmaC<C>(C(-1.0 / 3.0), Jx, bx);
+  f[2] = fmaC<C>(C(1.0 / 3.0), Jy, by);
+  f[4] = fmaC<C>(C(-1.0 / 3.0), Jy, by);
+  // diagonals: w = 1/36, bracket d + 3 tr P +- 9 P_xy + 3 e.J
+  const C bd = C(1.0 / 36.0) * fmaC<C>(C(3), t, d);
+  const C bp = fmaC<C>(C(0.25), pxy, bd);
+  const C bm = fmaC<C>(C(-0.25), pxy, bd);
+  const C sp = Jx + Jy;
+  const C sm = Jx - Jy;
+  f[5] = fmaC<C>(C(1.0 / 12.0), sp, bp);
+  f[7] = fmaC<C>(C(-1.0 / 12.0), sp, bp);
+  f[8] = fmaC<C>(C(1.0 / 12.0), sm, bm);
+  f[6] = fmaC<C>(C(-1.0 / 12.0), sm, bm);
+}
+
+// Deviation part of Eq. feqnoslip, w_q d(x), for an axis (1/9) or diagonal (1/36) link.
+template <typename C> __device__ __forceinline__ C wall_axis(C d) { return C(1.0 / 9.0) * d; }
+template <typename C> __device__ __forceinline__ C wall_diag(C d) { return C(1.0 / 36.0) * d; }
+
+// ----------------------------------------------------------------- target sums
+// Arrivals g[q] at a node (g[q] travelled along e_q, from x - e_q).  Grouped
+// by the source row: y-1 (q = 5, 2, 6), y (1, 0, 3), y+1 (8, 4, 7).  This
+// order is part of the contract between kernels: all of them use it.
+template <typename C> __device__ __forceinline__ C row_sum(C a, C b, C c) { return (a + b) + c; }
+template <typename C> __device__ __forceinline__ C row_dif(C a, C c) { return a - c; }
+template <typename C>
+__device__ __forceinline__ void finish(C sm, C xm, C s0, C x0, C sp, C xp, C &d, C &jx, C &jy) {
+  d = (sm + s0) + sp;
+  jx = (xm + x0) + xp;
+  jy = sm - sp;
+}
+
+// ----------------------------------------------------------------- kernel arguments
+struct StepArgs {
+  const void *src[3];  // d, jx, jy planes of the current parity
+  void *dst[3];        // planes of the next parity
+  const uint8_t *flags;
+  int nx, ny, pitch;   // pitch in values (a multiple of 64)
+  uint32_t periodic;   // bit 0 x, bit 1 y
+  double fx, fy;       // body force
+  double sc_d, sc_j;   // decode scales (stored * sc = value)
+  double is_d, is_j;   // encode scales (value * is = stored)
+};
+
+// Source coordinate along one axis: wrapped when periodic, -1 when outside.
+__device__ __forceinline__ int wrap_axis(int c, int n, bool periodic) {
+  if (c < 0) return periodic ? c + n : -1;
+  if (c >= n) return periodic ? c - n : -1;
+  return c;
+}
+
+template <int P>
+__device__ __forceinline__ void load_node(const StepArgs &a, long idx, typename Traits<P>::C &d,
+                                          typename Traits<P>::C &jx, typename Traits<P>::C &jy) {
+  using T = Traits<P>;
+  using S = typename T::S;
+  using C = typename T::C;
+  d = T::dec(static_cast<const S *>(a.src[0])[idx]);
+  jx = T::dec(static_cast<const S *>(a.src[1])[idx]);
+  jy = T::dec(static_cast<const S *>(a.src[2])[idx]);
+  if (T::kScaled) {
+    d *= C(a.sc_d);
+    jx *= C(a.sc_j);
+    jy *= C(a.sc_j);
+  }
+}
+
+}  // namespace lbt1

@@ -1,0 +1,25 @@
+// Host-side declarations shared by the runtime and the kernel table.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace lbt1 {
+
+enum : int { KIND_GATHER = 1, KIND_STRIP = 2 };
+
+// One built step kernel.  Gather kernels take (StepArgs); strip kernels take
+// (StepArgs, StripMap).
+struct StepKernel {
+  int prec, haswall, wall, kind, vec, rows;
+  const void *fn;
+  const char *name;
+};
+
+const StepKernel *step_kernels(int *count);
+const void *reduce_partial_kernel(int prec);
+const void *reduce_final_kernel();
+const void *batch_step_kernel(int prec, int vec_class);
+const void *batch_reduce_kernel(int prec);
+
+}  // namespace lbt1

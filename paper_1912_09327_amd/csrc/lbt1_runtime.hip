@@ -1,0 +1,815 @@
+// Host runtime and C ABI of liblbt1 (see include/lbt1.h).
+//
+// A grid owns (or borrows) one device allocation laid out as
+//   planes[parity 0][d, jx, jy] planes[parity 1][d, jx, jy] flags [snapshot d, jx, jy]
+//   reduction partials, reduction result
+// Each plane is ny rows of `pitch` values (pitch = nx rounded up to 64), the
+// structure-of-arrays form of the paper's R, U, V tables (Algorithm 1), with
+// x fastest so a wavefront's loads of one row are contiguous.  The two
+// parities are the paper's ping-pong copies; lbt1_step flips between them.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/lbt1.h"
+#include "lbt1_internal.hpp"
+#include "lbt1_runtime.hpp"
+
+namespace lbt1 {
+
+// ----------------------------------------------------------------- errors
+static thread_local std::string g_err;
+
+lbt1_status fail(lbt1_status st, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+lbt1_status hip_fail(hipError_t e, const char *what) {
+  return fail(LBT1_EDEVICE, "%s: %s (%d)", what, hipGetErrorString(e), (int)e);
+}
+
+void clear_error() { g_err.clear(); }
+
+// ----------------------------------------------------------------- layout
+size_t value_bytes(int prec) {
+  switch (prec) {
+    case LBT1_F64: return 8;
+    case LBT1_F32: return 4;
+    case LBT1_F16S:
+    case LBT1_BF16S: return 2;
+  }
+  return 0;
+}
+
+static size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+Layout layout_of(int nx, int ny, int prec, uint32_t options) {
+  Layout L{};
+  const size_t c = value_bytes(prec);
+  L.pitch = (int)round_up((size_t)nx, 64);
+  L.plane = round_up((size_t)L.pitch * ny * c, 256);
+  L.flags_off = 6 * L.plane;
+  L.flags_bytes = round_up((size_t)L.pitch * ny, 256);
+  size_t off = L.flags_off + L.flags_bytes;
+  if (options & LBT1_OPT_SNAPSHOT) {
+    L.snap_off = off;
+    off += 3 * L.plane;
+  } else {
+    L.snap_off = 0;
+  }
+  L.nparts = kReduceBlocks;
+  L.part_off = off;
+  off += round_up((size_t)L.nparts * 6 * sizeof(double), 256);
+  L.out_off = off;
+  off += 256;
+  L.total = off;
+  return L;
+}
+
+static bool valid_shape(int nx, int ny) { return nx >= 3 && ny >= 3 && nx <= 65536 && ny <= 65536; }
+static bool valid_prec(int p) { return p >= LBT1_F64 && p <= LBT1_BF16S; }
+
+static bool pow2_or_zero(double s) {
+  if (s == 0.0) return true;
+  if (!(s > 0.0) || !std::isfinite(s)) return false;
+  int e;
+  double m = std::frexp(s, &e);
+  return m == 0.5;
+}
+
+// ----------------------------------------------------------------- host codecs
+// Round a double to the nearest value with `mant` significand bits (round half
+// to even), normal exponent >= emin, gradual underflow below; returns +-inf
+// above `maxv`.  Used for IEEE binary16 (11 bits, emin -14, max 65504) and
+// bfloat16 (8 bits, emin -126, max (2 - 2^-7) 2^127).
+static double round_to_format(double x, int mant, int emin, double maxv) {
+  if (!std::isfinite(x) || x == 0.0) return x;
+  int e;
+  std::frexp(x, &e);               // x = m 2^e, 0.5 <= |m| < 1
+  int q = std::max(e, emin + 1) - mant;  // quantum exponent
+  double r = std::nearbyint(std::ldexp(x, -q));  // default rounding mode: to nearest even
+  double y = std::ldexp(r, q);
+  if (std::fabs(y) > maxv) return std::copysign(INFINITY, x);
+  return y;
+}
+
+static uint16_t encode_half(double v) {
+  double r = round_to_format(v, 11, -14, 65504.0);
+  _Float16 h = (_Float16)(float)r;  // exact: r is representable
+  uint16_t b;
+  std::memcpy(&b, &h, 2);
+  return b;
+}
+static uint16_t encode_bf16(double v) {
+  if (std::isnan(v)) return 0x7fc0;
+  double r = round_to_format(v, 8, -126, std::ldexp(255.0, 120));
+  float f = (float)r;  // exact
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  return (uint16_t)(u >> 16);
+}
+static double decode_half(uint16_t b) {
+  _Float16 h;
+  std::memcpy(&h, &b, 2);
+  return (double)(float)h;
+}
+static double decode_bf16(uint16_t b) {
+  uint32_t u = (uint32_t)b << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return (double)f;
+}
+
+void encode_values(int prec, const double *in, size_t n, double inv_scale, void *out) {
+  switch (prec) {
+    case LBT1_F64: {
+      double *o = (double *)out;
+      for (size_t i = 0; i < n; ++i) o[i] = in[i];
+      break;
+    }
+    case LBT1_F32: {
+      float *o = (float *)out;
+      for (size_t i = 0; i < n; ++i) o[i] = (float)in[i];
+      break;
+    }
+    case LBT1_F16S: {
+      uint16_t *o = (uint16_t *)out;
+      for (size_t i = 0; i < n; ++i) o[i] = encode_half(in[i] * inv_scale);
+      break;
+    }
+    case LBT1_BF16S: {
+      uint16_t *o = (uint16_t *)out;
+      for (size_t i = 0; i < n; ++i) o[i] = encode_bf16(in[i] * inv_scale);
+      break;
+    }
+  }
+}
+
+void decode_values(int prec, const void *in, size_t n, double scale, double *out) {
+  switch (prec) {
+    case LBT1_F64: {
+      const double *s = (const double *)in;
+      for (size_t i = 0; i < n; ++i) out[i] = s[i];
+      break;
+    }
+    case LBT1_F32: {
+      const float *s = (const float *)in;
+      for (size_t i = 0; i < n; ++i) out[i] = s[i];
+      break;
+    }
+    case LBT1_F16S: {
+      const uint16_t *s = (const uint16_t *)in;
+      for (size_t i = 0; i < n; ++i) out[i] = decode_half(s[i]) * scale;
+      break;
+    }
+    case LBT1_BF16S: {
+      const uint16_t *s = (const uint16_t *)in;
+      for (size_t i = 0; i < n; ++i) out[i] = decode_bf16(s[i]) * scale;
+      break;
+    }
+  }
+}
+
+// ----------------------------------------------------------------- device check
+static lbt1_status check_device(int *dev_out, int *cus) {
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess) return fail(LBT1_EDEVICE, "no HIP device is visible: hipGetDeviceCount: %s (%d)", hipGetErrorString(e), (int)e);
+  if (ndev <= 0) return fail(LBT1_EDEVICE, "no HIP device is visible");
+  int dev = 0;
+  if ((e = hipGetDevice(&dev)) != hipSuccess) return hip_fail(e, "hipGetDevice");
+  hipDeviceProp_t prop;
+  if ((e = hipGetDeviceProperties(&prop, dev)) != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(LBT1_EDEVICE, "device %d is %s; this library is built for gfx950", dev, prop.gcnArchName);
+  *dev_out = dev;
+  if (cus) *cus = prop.multiProcessorCount;
+  return LBT1_OK;
+}
+
+// ----------------------------------------------------------------- kernel selection
+static bool strip_fits(int nx, int vec) { return vec >= 1 && nx % vec == 0; }
+
+const StepKernel *find_kernel(int prec, bool haswall, int wall, int kind, int vec, int rows) {
+  int n = 0;
+  const StepKernel *t = step_kernels(&n);
+  for (int i = 0; i < n; ++i) {
+    const StepKernel &k = t[i];
+    if (k.prec != prec || k.kind != kind || (k.haswall != 0) != haswall) continue;
+    if (haswall && k.wall != wall) continue;
+    if (kind == KIND_STRIP && (k.vec != vec || k.rows != rows)) continue;
+    return &k;
+  }
+  return nullptr;
+}
+
+static std::mutex g_tune_mu;
+static std::map<std::tuple<int, int, int, int, int>, lbt1_kernel_config> g_tuned;
+
+static std::tuple<int, int, int, int, int> tune_key(const lbt1_grid *g) {
+  return std::make_tuple(g->prec, (int)g->haswall, g->haswall ? g->wall : 0, g->nx, g->ny);
+}
+
+lbt1_kernel_config heuristic_config(int prec, int nx, int ny) {
+  lbt1_kernel_config c{};
+  if ((long)nx * ny < 64 * 64) {
+    c.kernel = LBT1_KERNEL_GATHER;
+    return c;
+  }
+  c.kernel = LBT1_KERNEL_STRIP;
+  c.rows = 14;
+  c.waves = 0;
+  const int cands16[] = {8, 4, 2, 1}, cands32[] = {4, 2, 1}, cands64[] = {2, 1};
+  const int *cands = prec == LBT1_F64 ? cands64 : prec == LBT1_F32 ? cands32 : cands16;
+  const int nc = prec == LBT1_F64 ? 2 : prec == LBT1_F32 ? 3 : 4;
+  c.vec = 1;
+  for (int i = 0; i < nc; ++i) {
+    const int v = cands[i];
+    if (nx % v == 0 && 64 * v <= std::max(64, nx)) {
+      c.vec = v;
+      break;
+    }
+  }
+  return c;
+}
+
+// Resolve a configuration into a kernel and launch shape for grid g.
+lbt1_status bind_config(lbt1_grid *g, const lbt1_kernel_config &want, int cus) {
+  lbt1_kernel_config c = want;
+  if (c.kernel == LBT1_KERNEL_AUTO) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuned.find(tune_key(g));
+    c = it != g_tuned.end() ? it->second : heuristic_config(g->prec, g->nx, g->ny);
+  }
+  const StepKernel *k = nullptr;
+  if (c.kernel == LBT1_KERNEL_GATHER) {
+    k = find_kernel(g->prec, g->haswall, g->wall, KIND_GATHER, 0, 0);
+    c.vec = c.rows = c.waves = 0;
+  } else if (c.kernel == LBT1_KERNEL_STRIP) {
+    if (!strip_fits(g->nx, c.vec))
+      return fail(LBT1_EINVAL, "strip kernel: vec %d does not divide nx %d", c.vec, g->nx);
+    if (c.waves < 0 || c.waves > 32) return fail(LBT1_EINVAL, "waves %d out of range", c.waves);
+    k = find_kernel(g->prec, g->haswall, g->wall, KIND_STRIP, c.vec, c.rows);
+  } else {
+    return fail(LBT1_EINVAL, "unknown kernel family %d", c.kernel);
+  }
+  if (!k) return fail(LBT1_EINVAL, "no built kernel for vec %d rows %d at this precision", c.vec, c.rows);
+  g->kern = k;
+  g->cfg = c;
+  g->cfg.kernel = k->kind == KIND_GATHER ? LBT1_KERNEL_GATHER : LBT1_KERNEL_STRIP;
+  if (k->kind == KIND_GATHER) {
+    g->block = dim3(64, 4, 1);
+    g->grid = dim3((g->nx + 63) / 64, (g->ny + 3) / 4, 1);
+  } else {
+    StripMap &m = g->map;
+    m.strips_x = (g->nx + 64 * c.vec - 1) / (64 * c.vec);
+    m.strips_y = (g->ny + c.rows - 1) / c.rows;
+    const int strips = m.strips_x * m.strips_y;
+    m.units = (strips + 3) / 4;
+    int blocks;
+    if (c.waves > 0) {
+      // c.waves wavefronts per CU, 4 per block, a multiple of 8 blocks (one range per XCD)
+      blocks = std::max(8, (cus * c.waves / 4) / 8 * 8);
+      blocks = std::min(blocks, (m.units + 7) / 8 * 8);
+      m.persistent = 1;
+    } else {
+      blocks = (m.units + 7) / 8 * 8;
+      m.persistent = 0;
+    }
+    m.per_xcd = (m.units + 7) / 8;
+    g->block = dim3(256, 1, 1);
+    g->grid = dim3(blocks, 1, 1);
+  }
+  g->graph_valid = false;
+  return LBT1_OK;
+}
+
+StepArgs step_args(const lbt1_grid *g, int src_parity) {
+  StepArgs a{};
+  for (int q = 0; q < 3; ++q) {
+    a.src[q] = g->plane[src_parity][q];
+    a.dst[q] = g->plane[1 - src_parity][q];
+  }
+  a.flags = g->haswall ? g->flags : nullptr;
+  a.nx = g->nx;
+  a.ny = g->ny;
+  a.pitch = g->L.pitch;
+  a.periodic = g->periodic;
+  a.fx = g->F[0];
+  a.fy = g->F[1];
+  a.sc_d = g->sc[0];
+  a.sc_j = g->sc[1];
+  a.is_d = 1.0 / g->sc[0];
+  a.is_j = 1.0 / g->sc[1];
+  return a;
+}
+
+hipError_t launch_step(lbt1_grid *g, int src_parity, hipStream_t s) {
+  StepArgs a = step_args(g, src_parity);
+  if (g->kern->kind == KIND_GATHER) {
+    void *args[] = {&a};
+    return hipLaunchKernel(g->kern->fn, g->grid, g->block, args, 0, s);
+  }
+  StripMap m = g->map;
+  void *args[] = {&a, &m};
+  return hipLaunchKernel(g->kern->fn, g->grid, g->block, args, 0, s);
+}
+
+// A graph of kBurst step launches starting from parity p (kBurst is even, so
+// the parity after a replay is p again).
+static const int kBurst = 64;
+
+static lbt1_status build_burst(lbt1_grid *g, int p) {
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipGraphCreate(&graph, 0);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphCreate");
+  hipGraphNode_t prev = nullptr;
+  std::vector<StepArgs> argv(kBurst);
+  StripMap m = g->map;
+  for (int s = 0; s < kBurst; ++s) {
+    argv[s] = step_args(g, (p + s) & 1);
+    void *args_gather[] = {&argv[s]};
+    void *args_strip[] = {&argv[s], &m};
+    hipKernelNodeParams kp{};
+    kp.func = const_cast<void *>(g->kern->fn);
+    kp.gridDim = g->grid;
+    kp.blockDim = g->block;
+    kp.sharedMemBytes = 0;
+    kp.kernelParams = g->kern->kind == KIND_GATHER ? args_gather : args_strip;
+    kp.extra = nullptr;
+    hipGraphNode_t node;
+    e = hipGraphAddKernelNode(&node, graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
+    if (e != hipSuccess) {
+      hipGraphDestroy(graph);
+      return hip_fail(e, "hipGraphAddKernelNode");
+    }
+    prev = node;
+  }
+  if (g->burst[p]) hipGraphExecDestroy(g->burst[p]);
+  g->burst[p] = nullptr;
+  e = hipGraphInstantiate(&g->burst[p], graph, nullptr, nullptr, 0);
+  hipGraphDestroy(graph);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+  return LBT1_OK;
+}
+
+static void drop_bursts(lbt1_grid *g) {
+  for (int p = 0; p < 2; ++p)
+    if (g->burst[p]) {
+      hipGraphExecDestroy(g->burst[p]);
+      g->burst[p] = nullptr;
+    }
+  g->graph_valid = false;
+}
+
+lbt1_status enqueue_steps(lbt1_grid *g, int64_t n, hipStream_t s, bool use_graph) {
+  hipError_t e;
+  if (use_graph && n >= kBurst) {
+    if (!g->graph_valid) {
+      drop_bursts(g);
+      g->graph_valid = true;
+    }
+    while (n >= kBurst) {
+      const int p = g->parity;
+      if (!g->burst[p]) {
+        lbt1_status st = build_burst(g, p);
+        if (st) return st;
+      }
+      if ((e = hipGraphLaunch(g->burst[p], s)) != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+      n -= kBurst;
+      g->steps += kBurst;
+    }
+  }
+  for (int64_t i = 0; i < n; ++i) {
+    if ((e = launch_step(g, g->parity, s)) != hipSuccess) return hip_fail(e, "step launch");
+    g->parity ^= 1;
+    g->steps += 1;
+  }
+  return LBT1_OK;
+}
+
+lbt1_status enqueue_reduce(lbt1_grid *g, uint32_t what, hipStream_t s) {
+  ReduceArgs a{};
+  for (int q = 0; q < 3; ++q) {
+    a.cur[q] = g->plane[g->parity][q];
+    a.snap[q] = g->snap[q];
+  }
+  a.flags = g->haswall ? g->flags : nullptr;
+  a.nx = g->nx;
+  a.ny = g->ny;
+  a.pitch = g->L.pitch;
+  a.sc_d = g->sc[0];
+  a.sc_j = g->sc[1];
+  a.what = what;
+  a.partials = g->partials;
+  const long n = (long)g->nx * g->ny;
+  const int blocks = (int)std::min<long>(g->L.nparts, std::max<long>(1, (n + 1023) / 1024));
+  void *args[] = {&a};
+  hipError_t e = hipLaunchKernel(reduce_partial_kernel(g->prec), dim3(blocks), dim3(256), args, 0, s);
+  if (e != hipSuccess) return hip_fail(e, "reduce launch");
+  const double *parts = g->partials;
+  int np = blocks;
+  double *out = g->red_out;
+  void *args2[] = {&parts, &np, &out};
+  e = hipLaunchKernel(reduce_final_kernel(), dim3(1), dim3(64), args2, 0, s);
+  if (e != hipSuccess) return hip_fail(e, "reduce launch");
+  return LBT1_OK;
+}
+
+}  // namespace lbt1
+
+using namespace lbt1;
+
+// =================================================================== C ABI
+extern "C" {
+
+const char *lbt1_last_error(void) { return g_err.c_str(); }
+
+size_t lbt1_grid_bytes(int32_t nx, int32_t ny, int32_t prec, uint32_t options) {
+  if (!valid_shape(nx, ny) || !valid_prec(prec)) return 0;
+  return layout_of(nx, ny, prec, options).total;
+}
+
+lbt1_status lbt1_create_grid(const lbt1_grid_desc *d, lbt1_grid **out) {
+  clear_error();
+  if (!d || !out) return fail(LBT1_EINVAL, "null argument");
+  *out = nullptr;
+  if (!valid_shape(d->nx, d->ny)) return fail(LBT1_EINVAL, "grid %d x %d: each side must be 3..65536", d->nx, d->ny);
+  if (!valid_prec(d->prec)) return fail(LBT1_EINVAL, "unknown precision %d", d->prec);
+  if (d->wall != LBT1_WALL_PAPER && d->wall != LBT1_WALL_HALFWAY) return fail(LBT1_EINVAL, "unknown wall rule %d", d->wall);
+  if (d->periodic & ~3u) return fail(LBT1_EINVAL, "periodic mask %u", d->periodic);
+  if (d->options & ~(uint32_t)LBT1_OPT_SNAPSHOT) return fail(LBT1_EINVAL, "unknown options %u", d->options);
+  if (!std::isfinite(d->force[0]) || !std::isfinite(d->force[1])) return fail(LBT1_EINVAL, "force must be finite");
+  if (!pow2_or_zero(d->scale[0]) || !pow2_or_zero(d->scale[1]))
+    return fail(LBT1_EINVAL, "scales must be 0 or positive powers of two");
+  int dev = 0, cus = 0;
+  lbt1_status st = check_device(&dev, &cus);
+  if (st) return st;
+  lbt1_grid *g = new (std::nothrow) lbt1_grid();
+  if (!g) return fail(LBT1_ENOMEM, "host allocation");
+  g->device = dev;
+  g->cus = cus;
+  g->nx = d->nx;
+  g->ny = d->ny;
+  g->periodic = d->periodic;
+  g->prec = d->prec;
+  g->wall = d->wall;
+  g->options = d->options;
+  g->F[0] = d->force[0];
+  g->F[1] = d->force[1];
+  const bool scaled = d->prec == LBT1_F16S || d->prec == LBT1_BF16S;
+  g->sc[0] = (scaled && d->scale[0] != 0.0) ? d->scale[0] : 1.0;
+  g->sc[1] = (scaled && d->scale[1] != 0.0) ? d->scale[1] : 1.0;
+  g->L = layout_of(d->nx, d->ny, d->prec, d->options);
+  hipError_t e;
+  if (d->device_buffer) {
+    if (d->device_bytes < g->L.total) {
+      delete g;
+      return fail(LBT1_ENOMEM, "device buffer has %zu bytes, grid needs %zu", d->device_bytes, g->L.total);
+    }
+    if (((uintptr_t)d->device_buffer) % 256) {
+      delete g;
+      return fail(LBT1_EINVAL, "device buffer must be 256-byte aligned");
+    }
+    g->base = (char *)d->device_buffer;
+    g->own_mem = false;
+  } else {
+    void *p = nullptr;
+    if ((e = hipMalloc(&p, g->L.total)) != hipSuccess) {
+      delete g;
+      return fail(LBT1_ENOMEM, "hipMalloc(%zu): %s", g->L.total, hipGetErrorString(e));
+    }
+    g->base = (char *)p;
+    g->own_mem = true;
+  }
+  if (d->stream) {
+    g->stream = (hipStream_t)d->stream;
+    g->own_stream = false;
+  } else {
+    if ((e = hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking)) != hipSuccess) {
+      if (g->own_mem) hipFree(g->base);
+      delete g;
+      return hip_fail(e, "hipStreamCreate");
+    }
+    g->own_stream = true;
+  }
+  for (int p = 0; p < 2; ++p)
+    for (int q = 0; q < 3; ++q) g->plane[p][q] = g->base + (size_t)(3 * p + q) * g->L.plane;
+  g->flags = (uint8_t *)(g->base + g->L.flags_off);
+  for (int q = 0; q < 3; ++q) g->snap[q] = (d->options & LBT1_OPT_SNAPSHOT) ? g->base + g->L.snap_off + q * g->L.plane : nullptr;
+  g->partials = (double *)(g->base + g->L.part_off);
+  g->red_out = (double *)(g->base + g->L.out_off);
+  if ((e = hipHostMalloc((void **)&g->red_host, 8 * sizeof(double), hipHostMallocDefault)) != hipSuccess) {
+    if (g->own_stream) hipStreamDestroy(g->stream);
+    if (g->own_mem) hipFree(g->base);
+    delete g;
+    return hip_fail(e, "hipHostMalloc");
+  }
+  g->cfg.kernel = LBT1_KERNEL_AUTO;
+  *out = g;
+  return LBT1_OK;
+}
+
+lbt1_status lbt1_set_geometry(lbt1_grid *g, const uint8_t *flags, const double *rho, const double *jx,
+                              const double *jy) {
+  clear_error();
+  if (!g) return fail(LBT1_EINVAL, "null grid");
+  if (g->batch) return fail(LBT1_ESTATE, "grid is resident in a batch");
+  const int nx = g->nx, ny = g->ny, pitch = g->L.pitch;
+  const size_t n = (size_t)nx * ny;
+  bool any_fixed = false, any_nonfluid = false;
+  int64_t fluid = 0;
+  if (flags) {
+    for (size_t i = 0; i < n; ++i) {
+      const uint8_t f = flags[i];
+      if (f > LBT1_FIXED) return fail(LBT1_EINVAL, "flag %u at node %zu is not FLUID/SOLID/FIXED", f, i);
+      any_fixed |= f == LBT1_FIXED;
+      any_nonfluid |= f != LBT1_FLUID;
+      fluid += f == LBT1_FLUID;
+    }
+  } else {
+    fluid = (int64_t)n;
+  }
+  if (any_fixed && !rho && !jx && !jy) return fail(LBT1_EINVAL, "FIXED nodes need moments");
+  for (size_t i = 0; rho && i < n; ++i)
+    if (!(rho[i] > 0.0) || !std::isfinite(rho[i])) return fail(LBT1_EINVAL, "rho[%zu] = %g must be finite and > 0", i, rho[i]);
+  for (size_t i = 0; jx && i < n; ++i)
+    if (!std::isfinite(jx[i])) return fail(LBT1_EINVAL, "jx[%zu] is not finite", i);
+  for (size_t i = 0; jy && i < n; ++i)
+    if (!std::isfinite(jy[i])) return fail(LBT1_EINVAL, "jy[%zu] is not finite", i);
+
+  // Host staging in storage format with padded rows.
+  const size_t c = value_bytes(g->prec);
+  const size_t plane_vals = (size_t)pitch * ny;
+  std::vector<char> stage;
+  std::vector<uint8_t> fstage;
+  try {
+    stage.assign(3 * plane_vals * c, 0);
+    fstage.assign(plane_vals, LBT1_SOLID);
+  } catch (...) {
+    return fail(LBT1_ENOMEM, "host staging");
+  }
+  std::vector<double> row(nx);
+  for (int y = 0; y < ny; ++y) {
+    for (int q = 0; q < 3; ++q) {
+      const double *src = q == 0 ? rho : q == 1 ? jx : jy;
+      for (int x = 0; x < nx; ++x) {
+        const size_t i = (size_t)y * nx + x;
+        row[x] = src ? (q == 0 ? src[i] - 1.0 : src[i]) : 0.0;
+      }
+      encode_values(g->prec, row.data(), nx, 1.0 / g->sc[q == 0 ? 0 : 1],
+                    stage.data() + (q * plane_vals + (size_t)y * pitch) * c);
+    }
+    for (int x = 0; x < nx; ++x) fstage[(size_t)y * pitch + x] = flags ? flags[(size_t)y * nx + x] : LBT1_FLUID;
+  }
+  hipError_t e;
+  if ((e = hipSetDevice(g->device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
+  if ((e = hipStreamSynchronize(g->stream)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  for (int p = 0; p < 2; ++p)
+    for (int q = 0; q < 3; ++q)
+      if ((e = hipMemcpy(g->plane[p][q], stage.data() + q * plane_vals * c, plane_vals * c, hipMemcpyHostToDevice)) != hipSuccess)
+        return hip_fail(e, "hipMemcpy H2D");
+  for (int q = 0; q < 3 && g->snap[0]; ++q)
+    if ((e = hipMemcpy(g->snap[q], stage.data() + q * plane_vals * c, plane_vals * c, hipMemcpyHostToDevice)) != hipSuccess)
+      return hip_fail(e, "hipMemcpy H2D");
+  if ((e = hipMemcpy(g->flags, fstage.data(), plane_vals, hipMemcpyHostToDevice)) != hipSuccess)
+    return hip_fail(e, "hipMemcpy H2D");
+  g->haswall = any_nonfluid || g->periodic != 3u;
+  g->fluid = fluid;
+  g->parity = 0;
+  g->steps = 0;
+  g->geometry = true;
+  drop_bursts(g);
+  lbt1_kernel_config want{};
+  if (g->user_cfg) want = g->cfg;
+  lbt1_status st = bind_config(g, want, g->cus);
+  if (st) return st;
+  return LBT1_OK;
+}
+
+lbt1_status lbt1_step(lbt1_grid *g, int64_t n) {
+  clear_error();
+  if (!g) return fail(LBT1_EINVAL, "null grid");
+  if (n < 0) return fail(LBT1_EINVAL, "negative step count");
+  if (!g->geometry) return fail(LBT1_ESTATE, "lbt1_step before lbt1_set_geometry");
+  if (g->batch) return fail(LBT1_ESTATE, "grid is resident in a batch");
+  hipError_t e;
+  if ((e = hipSetDevice(g->device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
+  return enqueue_steps(g, n, g->stream, true);
+}
+
+lbt1_status lbt1_sync(lbt1_grid *g) {
+  clear_error();
+  if (!g) return fail(LBT1_EINVAL, "null grid");
+  hipError_t e = hipStreamSynchronize(g->stream);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  return LBT1_OK;
+}
+
+lbt1_status lbt1_read_moments(lbt1_grid *g, double *rho, double *jx, double *jy) {
+  clear_error();
+  if (!g) return fail(LBT1_EINVAL, "null grid");
+  if (!g->geometry) return fail(LBT1_ESTATE, "no geometry set");
+  const int nx = g->nx, ny = g->ny;
+  const size_t c = value_bytes(g->prec);
+  std::vector<char> stage;
+  try {
+    stage.resize((size_t)nx * ny * c);
+  } catch (...) {
+    return fail(LBT1_ENOMEM, "host staging");
+  }
+  hipError_t e;
+  if ((e = hipSetDevice(g->device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
+  if ((e = hipStreamSynchronize(g->stream)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  for (int q = 0; q < 3; ++q) {
+    double *dst = q == 0 ? rho : q == 1 ? jx : jy;
+    if (!dst) continue;
+    if ((e = hipMemcpy2D(stage.data(), (size_t)nx * c, g->plane[g->parity][q], (size_t)g->L.pitch * c, (size_t)nx * c, ny,
+                         hipMemcpyDeviceToHost)) != hipSuccess)
+      return hip_fail(e, "hipMemcpy2D D2H");
+    decode_values(g->prec, stage.data(), (size_t)nx * ny, g->sc[q == 0 ? 0 : 1], dst);
+    if (q == 0)
+      for (size_t i = 0; i < (size_t)nx * ny; ++i) dst[i] += 1.0;
+  }
+  return LBT1_OK;
+}
+
+lbt1_status lbt1_reduce(lbt1_grid *g, uint32_t what, double *out) {
+  clear_error();
+  if (!g || !out) return fail(LBT1_EINVAL, "null argument");
+  if (what & ~15u) return fail(LBT1_EINVAL, "unknown reduce bits %u", what);
+  if (!g->geometry) return fail(LBT1_ESTATE, "no geometry set");
+  if ((what & LBT1_REDUCE_RESIDUAL) && !g->snap[0]) return fail(LBT1_EINVAL, "grid was created without LBT1_OPT_SNAPSHOT");
+  if (g->batch) return fail(LBT1_ESTATE, "grid is resident in a batch");
+  hipError_t e;
+  if ((e = hipSetDevice(g->device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
+  lbt1_status st = enqueue_reduce(g, what, g->stream);
+  if (st) return st;
+  if ((e = hipMemcpyAsync(g->red_host, g->red_out, 6 * sizeof(double), hipMemcpyDeviceToHost, g->stream)) != hipSuccess)
+    return hip_fail(e, "hipMemcpyAsync D2H");
+  if ((e = hipStreamSynchronize(g->stream)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  const double *r = g->red_host;
+  if (what & LBT1_REDUCE_MASS) out[0] = r[5] + r[0];
+  if (what & LBT1_REDUCE_MOMENTUM) {
+    out[1] = r[1];
+    out[2] = r[2];
+  }
+  if (what & LBT1_REDUCE_RESIDUAL) out[3] = r[3];
+  if (what & LBT1_REDUCE_NONFINITE) out[4] = r[4];
+  out[5] = r[5];
+  return LBT1_OK;
+}
+
+lbt1_status lbt1_destroy_grid(lbt1_grid *g) {
+  clear_error();
+  if (!g) return LBT1_OK;
+  if (g->batch) return fail(LBT1_ESTATE, "grid is resident in a batch; evict it first");
+  hipSetDevice(g->device);
+  hipStreamSynchronize(g->stream);
+  drop_bursts(g);
+  if (g->red_host) hipHostFree(g->red_host);
+  if (g->own_stream) hipStreamDestroy(g->stream);
+  if (g->own_mem) hipFree(g->base);
+  delete g;
+  return LBT1_OK;
+}
+
+lbt1_status lbt1_set_kernel(lbt1_grid *g, const lbt1_kernel_config *cfg) {
+  clear_error();
+  if (!g || !cfg) return fail(LBT1_EINVAL, "null argument");
+  if (!g->geometry) {
+    g->cfg = *cfg;
+    g->user_cfg = cfg->kernel != LBT1_KERNEL_AUTO;
+    return LBT1_OK;
+  }
+  lbt1_kernel_config old = g->cfg;
+  const StepKernel *oldk = g->kern;
+  lbt1_status st = bind_config(g, *cfg, g->cus);
+  if (st) {
+    g->cfg = old;
+    g->kern = oldk;
+    bind_config(g, old, g->cus);
+    return st;
+  }
+  g->user_cfg = cfg->kernel != LBT1_KERNEL_AUTO;
+  drop_bursts(g);
+  return LBT1_OK;
+}
+
+lbt1_status lbt1_get_kernel(lbt1_grid *g, lbt1_kernel_config *cfg, char *name, size_t cap) {
+  clear_error();
+  if (!g) return fail(LBT1_EINVAL, "null grid");
+  if (!g->kern) return fail(LBT1_ESTATE, "no kernel bound (set the geometry first)");
+  if (cfg) *cfg = g->cfg;
+  if (name && cap) {
+    std::strncpy(name, g->kern->name, cap - 1);
+    name[cap - 1] = 0;
+  }
+  return LBT1_OK;
+}
+
+lbt1_status lbt1_autotune(lbt1_grid *g, int32_t steps, int32_t reps, lbt1_kernel_config *best,
+                          double *ms_per_step) {
+  clear_error();
+  if (!g) return fail(LBT1_EINVAL, "null grid");
+  if (!g->geometry) return fail(LBT1_ESTATE, "no geometry set");
+  if (g->batch) return fail(LBT1_ESTATE, "grid is resident in a batch");
+  if (steps < 2 || reps < 1) return fail(LBT1_EINVAL, "steps >= 2 and reps >= 1 required");
+  hipError_t e;
+  if ((e = hipSetDevice(g->device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
+  if ((e = hipStreamSynchronize(g->stream)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  // scratch clone: both parities and the flags
+  lbt1_grid t = *g;
+  t.burst[0] = t.burst[1] = nullptr;
+  t.graph_valid = false;
+  void *p = nullptr;
+  if ((e = hipMalloc(&p, 6 * g->L.plane + g->L.flags_bytes)) != hipSuccess)
+    return fail(LBT1_ENOMEM, "autotune scratch: %s", hipGetErrorString(e));
+  t.base = (char *)p;
+  for (int a = 0; a < 2; ++a)
+    for (int q = 0; q < 3; ++q) t.plane[a][q] = t.base + (size_t)(3 * a + q) * g->L.plane;
+  t.flags = (uint8_t *)(t.base + 6 * g->L.plane);
+  for (int a = 0; a < 2; ++a)
+    for (int q = 0; q < 3; ++q) hipMemcpyAsync(t.plane[a][q], g->plane[a][q], g->L.plane, hipMemcpyDeviceToDevice, g->stream);
+  hipMemcpyAsync(t.flags, g->flags, g->L.flags_bytes, hipMemcpyDeviceToDevice, g->stream);
+  hipEvent_t e0, e1;
+  hipEventCreate(&e0);
+  hipEventCreate(&e1);
+  std::vector<lbt1_kernel_config> cands;
+  {
+    lbt1_kernel_config c{};
+    c.kernel = LBT1_KERNEL_GATHER;
+    cands.push_back(c);
+  }
+  const int vecs[] = {1, 2, 4, 8};
+  const int rows[] = {14, 30};
+  const int waves[] = {0, 8, 16};
+  for (int v : vecs)
+    for (int r : rows)
+      for (int w : waves) {
+        if (!strip_fits(g->nx, v)) continue;
+        if (!find_kernel(g->prec, g->haswall, g->wall, KIND_STRIP, v, r)) continue;
+        if (64 * v > 2 * std::max(64, g->nx)) continue;
+        lbt1_kernel_config c{};
+        c.kernel = LBT1_KERNEL_STRIP;
+        c.vec = v;
+        c.rows = r;
+        c.waves = w;
+        cands.push_back(c);
+      }
+  double best_ms = 1e300;
+  lbt1_kernel_config bc = g->cfg;
+  lbt1_status st = LBT1_OK;
+  for (const auto &c : cands) {
+    if (bind_config(&t, c, g->cus) != LBT1_OK) continue;
+    double cbest = 1e300;
+    for (int r = 0; r < reps + 1 && st == LBT1_OK; ++r) {
+      hipEventRecord(e0, g->stream);
+      st = enqueue_steps(&t, steps, g->stream, false);
+      hipEventRecord(e1, g->stream);
+      hipEventSynchronize(e1);
+      float ms = 0;
+      hipEventElapsedTime(&ms, e0, e1);
+      if (r > 0) cbest = std::min(cbest, (double)ms / steps);  // first run warms up
+    }
+    if (st) break;
+    if (cbest < best_ms) {
+      best_ms = cbest;
+      bc = t.cfg;
+    }
+  }
+  hipStreamSynchronize(g->stream);
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  hipFree(p);
+  if (st) return st;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned[tune_key(g)] = bc;
+  }
+  st = bind_config(g, bc, g->cus);
+  if (st) return st;
+  g->user_cfg = true;
+  drop_bursts(g);
+  if (best) *best = bc;
+  if (ms_per_step) *ms_per_step = best_ms;
+  return LBT1_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,562 @@
+// LBMTau1 step kernels for gfx950 (templates; instantiated in lbt1_kernels.hip).
+//
+// Two kernel families compute the same update with the same operation order
+// (the per-source emission of lbt1_device.hpp and the per-target sums in
+// `finish`), so their results are bitwise identical:
+//
+//  * gather: one thread per node reads its nine upwind neighbours.  Simple,
+//    any size; the nine reads per node are served by the caches.
+//  * strip: one wavefront walks a strip of NY rows; each lane owns VEC
+//    adjacent columns.  Every source node's moments are read once per strip
+//    and its nine emissions computed once; the emissions that cross to the
+//    neighbouring column go through a one-lane shuffle, and the two columns
+//    just outside the strip are computed once per strip by a pre-pass whose
+//    lanes each take one (row, side) pair.  A strip reads its NY rows plus one
+//    halo row above and below.
+#pragma once
+#include <type_traits>
+
+#include "lbt1_args.hpp"
+#include "lbt1_device.hpp"
+
+namespace lbt1 {
+
+template <typename S, int VEC>
+struct alignas(sizeof(S) * VEC) Pack {
+  S v[VEC];
+};
+
+__device__ __forceinline__ float lane_read(float v, int l) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+}
+__device__ __forceinline__ double lane_read(double v, int l) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+__device__ __forceinline__ int lane_read(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+
+// ================================================================ gather kernel
+template <int P, bool HASWALL, int WALL>
+__device__ __forceinline__ void gather_node(const StepArgs &a, int x, int y) {
+  using T = Traits<P>;
+  using C = typename T::C;
+  using S = typename T::S;
+  const long i = (long)y * a.pitch + x;
+  if (HASWALL && a.flags[i] != NODE_FLUID) return;  // held in both parities
+  const C Fx = C(a.fx), Fy = C(a.fy);
+  C d0, jx0, jy0;
+  load_node<P>(a, i, d0, jx0, jy0);
+  C own[9];
+  emit<C>(d0, jx0, jy0, Fx, Fy, own);
+  C g[9];
+  g[0] = own[0];
+#pragma unroll
+  for (int q = 1; q < 9; ++q) {
+    const int sx = wrap_axis(x - kEx[q], a.nx, a.periodic & 1u);
+    const int sy = wrap_axis(y - kEy[q], a.ny, a.periodic & 2u);
+    bool solid = (sx < 0) || (sy < 0);
+    const long s = solid ? 0 : (long)sy * a.pitch + sx;
+    if (HASWALL && !solid) solid = a.flags[s] == NODE_SOLID;
+    if (!solid) {
+      C d, jx, jy;
+      load_node<P>(a, s, d, jx, jy);
+      C f[9];
+      emit<C>(d, jx, jy, Fx, Fy, f);
+      g[q] = f[q];
+    } else if (WALL == WALL_PAPER) {
+      g[q] = (q <= 4) ? wall_axis<C>(d0) : wall_diag<C>(d0);
+    } else {
+      g[q] = own[kInv[q]];
+    }
+  }
+  C dn, jxn, jyn;
+  finish<C>(row_sum(g[5], g[2], g[6]), row_dif(g[5], g[6]), row_sum(g[1], g[0], g[3]),
+            row_dif(g[1], g[3]), row_sum(g[8], g[4], g[7]), row_dif(g[8], g[7]), dn, jxn, jyn);
+  if (T::kScaled) {
+    dn *= C(a.is_d);
+    jxn *= C(a.is_j);
+    jyn *= C(a.is_j);
+  }
+  static_cast<S *>(a.dst[0])[i] = T::enc(dn);
+  static_cast<S *>(a.dst[1])[i] = T::enc(jxn);
+  static_cast<S *>(a.dst[2])[i] = T::enc(jyn);
+}
+
+// blockDim (64, 4); grid (ceil(nx/64), ceil(ny/4))
+template <int P, bool HASWALL, int WALL>
+__global__ void __launch_bounds__(256) k_step_gather(StepArgs a) {
+  const int x = blockIdx.x * 64 + threadIdx.x;
+  const int y = blockIdx.y * 4 + threadIdx.y;
+  if (x >= a.nx || y >= a.ny) return;
+  gather_node<P, HASWALL, WALL>(a, x, y);
+}
+
+// ================================================================ strip kernel
+template <typename C, int VEC>
+struct ArrW {  // arrivals from one source row, three per target column, with wall bits
+  C a[3][VEC];
+  uint32_t sb;  // bit 3*v + k: the source of a[k][v] is a wall
+};
+template <typename C, int VEC>
+struct ArrS {  // the same arrivals already reduced (no walls): row sum and x difference
+  C s[VEC];
+  C x[VEC];
+};
+
+
+template <int P, bool HASWALL, int WALL, int VEC, int NY>
+__device__ __forceinline__ void strip_body(const StepArgs &a, const int cx0, const int y0,
+                                           const int lane) {
+  using T = Traits<P>;
+  using C = typename T::C;
+  using S = typename T::S;
+  using SP = Pack<S, VEC>;
+  using FP = Pack<uint8_t, VEC>;
+  static_assert(NY % 2 == 0 && NY + 2 <= 32, "strip height");
+
+  const int nx = a.nx, ny = a.ny;
+  const long pitch = a.pitch;
+  const bool px = a.periodic & 1u, py = a.periodic & 2u;
+  const C Fx = C(a.fx), Fy = C(a.fy);
+  const C sd = C(a.sc_d), sj = C(a.sc_j), ed = C(a.is_d), ej = C(a.is_j);
+  const S *__restrict__ s0 = static_cast<const S *>(a.src[0]);
+  const S *__restrict__ s1 = static_cast<const S *>(a.src[1]);
+  const S *__restrict__ s2 = static_cast<const S *>(a.src[2]);
+  S *__restrict__ d0p = static_cast<S *>(a.dst[0]);
+  S *__restrict__ d1p = static_cast<S *>(a.dst[1]);
+  S *__restrict__ d2p = static_cast<S *>(a.dst[2]);
+  const int xc = cx0 + lane * VEC;
+  const bool lane_ok = xc < nx;
+  const int last_lane = min(63, (nx - 1 - cx0) / VEC);
+
+  // ---- pre-pass: emissions of the two columns just outside the strip.
+  // Lane i < 32 takes the left column at row y0-1+i (it needs the emissions
+  // heading +x: q = 1, 5, 8); lane 32+i the right one (q = 3, 6, 7).
+  C h0 = C(0), h1 = C(0), h2 = C(0);
+  int hs = 1;
+  {
+    const int side = lane >> 5, i = lane & 31;
+    if (i < NY + 2) {
+      const int r = wrap_axis(y0 - 1 + i, ny, py);
+      int c = side == 0 ? cx0 - 1 : cx0 + 64 * VEC;
+      if (side == 1 && c >= nx) c = nx;
+      c = wrap_axis(c, nx, px);
+      if (r >= 0 && c >= 0) {
+        const long idx = (long)r * pitch + c;
+        if (!HASWALL || a.flags[idx] != NODE_SOLID) {
+          C d = T::dec(s0[idx]), jx = T::dec(s1[idx]), jy = T::dec(s2[idx]);
+          if (T::kScaled) {
+            d *= sd;
+            jx *= sj;
+            jy *= sj;
+          }
+          C f[9];
+          emit<C>(d, jx, jy, Fx, Fy, f);
+          h0 = side == 0 ? f[1] : f[3];
+          h1 = side == 0 ? f[5] : f[6];
+          h2 = side == 0 ? f[8] : f[7];
+          hs = 0;
+        }
+      }
+    }
+  }
+
+  using Arr = typename std::conditional<HASWALL, ArrW<C, VEC>, ArrS<C, VEC>>::type;
+  Arr upA, upB, lev;
+  C own_d[VEC];
+  C own_f[HASWALL && WALL == WALL_HALFWAY ? 9 : 1][VEC];
+  SP own_raw[3];
+  uint32_t own_fluid = 0;
+  (void)own_d;
+  (void)own_f;
+  (void)own_fluid;
+
+  auto body = [&](const int i, Arr &up_old) __attribute__((always_inline)) {
+    const int r = y0 - 1 + i;
+    const int rr = wrap_axis(r, ny, py);
+    const bool row_ok = rr >= 0;
+    SP raw[3];
+    FP fl;
+    if (row_ok && lane_ok) {
+      const long idx = (long)rr * pitch + xc;
+      raw[0] = *reinterpret_cast<const SP *>(s0 + idx);
+      raw[1] = *reinterpret_cast<const SP *>(s1 + idx);
+      raw[2] = *reinterpret_cast<const SP *>(s2 + idx);
+      if (HASWALL) fl = *reinterpret_cast<const FP *>(a.flags + idx);
+    } else {
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) {
+        raw[0].v[v] = raw[1].v[v] = raw[2].v[v] = S(0);
+        fl.v[v] = row_ok ? NODE_FLUID : NODE_SOLID;
+      }
+    }
+    C f[VEC][9];
+    C dd[VEC];
+    uint32_t sbits = 0, fbits = 0;
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) {
+      C d = T::dec(raw[0].v[v]), jx = T::dec(raw[1].v[v]), jy = T::dec(raw[2].v[v]);
+      if (T::kScaled) {
+        d *= sd;
+        jx *= sj;
+        jy *= sj;
+      }
+      dd[v] = d;
+      emit<C>(d, jx, jy, Fx, Fy, f[v]);
+      if (HASWALL) {
+        sbits |= (uint32_t)(fl.v[v] == NODE_SOLID) << v;
+        fbits |= (uint32_t)(fl.v[v] == NODE_FLUID) << v;
+      }
+    }
+    (void)dd;
+    (void)fbits;
+    // neighbour-lane emissions: heading +x from the lane on the left, -x from the right
+    C L1 = __shfl_up(f[VEC - 1][1], 1);
+    C L5 = __shfl_up(f[VEC - 1][5], 1);
+    C L8 = __shfl_up(f[VEC - 1][8], 1);
+    C R3 = __shfl_down(f[0][3], 1);
+    C R6 = __shfl_down(f[0][6], 1);
+    C R7 = __shfl_down(f[0][7], 1);
+    int Ls = 0, Rs = 0;
+    if (HASWALL) {
+      Ls = __shfl_up((int)((sbits >> (VEC - 1)) & 1u), 1);
+      Rs = __shfl_down((int)(sbits & 1u), 1);
+    }
+    {
+      const C e0 = lane_read(h0, i), e1 = lane_read(h1, i), e2 = lane_read(h2, i);
+      const C g0 = lane_read(h0, 32 + i), g1 = lane_read(h1, 32 + i), g2 = lane_read(h2, 32 + i);
+      if (lane == 0) {
+        L1 = e0;
+        L5 = e1;
+        L8 = e2;
+      }
+      if (lane == last_lane) {
+        R3 = g0;
+        R6 = g1;
+        R7 = g2;
+      }
+      if (HASWALL) {
+        const int es = lane_read(hs, i), gs = lane_read(hs, 32 + i);
+        if (lane == 0) Ls = es;
+        if (lane == last_lane) Rs = gs;
+      }
+    }
+    // wall bits of the left / own / right source of column v
+    auto bit_l = [&](int v) -> uint32_t { return v > 0 ? (sbits >> (v - 1)) & 1u : (uint32_t)Ls; };
+    auto bit_r = [&](int v) -> uint32_t { return v < VEC - 1 ? (sbits >> (v + 1)) & 1u : (uint32_t)Rs; };
+
+    // ---- target row r - 1: arrivals from rows r - 2 (up_old), r - 1 (lev), r (here)
+    if (i >= 2) {
+      const int t = r - 1;
+      SP out[3];
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) {
+        const C a8 = v > 0 ? f[v - 1][8] : L8;
+        const C a4 = f[v][4];
+        const C a7 = v < VEC - 1 ? f[v + 1][7] : R7;
+        C dn, jxn, jyn;
+        if constexpr (HASWALL) {
+          const uint32_t ub = up_old.sb >> (3 * v), lb = lev.sb >> (3 * v);
+          C w5, w2, w6, w1, w3, w8, w4, w7;
+          if constexpr (WALL == WALL_PAPER) {
+            w2 = w1 = w3 = w4 = wall_axis<C>(own_d[v]);
+            w5 = w6 = w8 = w7 = wall_diag<C>(own_d[v]);
+          } else {
+            w5 = own_f[7][v];
+            w2 = own_f[4][v];
+            w6 = own_f[8][v];
+            w1 = own_f[3][v];
+            w3 = own_f[1][v];
+            w8 = own_f[6][v];
+            w4 = own_f[2][v];
+            w7 = own_f[5][v];
+          }
+          const C g5 = (ub & 1u) ? w5 : up_old.a[0][v];
+          const C g2 = (ub & 2u) ? w2 : up_old.a[1][v];
+          const C g6 = (ub & 4u) ? w6 : up_old.a[2][v];
+          const C g1 = (lb & 1u) ? w1 : lev.a[0][v];
+          const C g0 = lev.a[1][v];
+          const C g3 = (lb & 4u) ? w3 : lev.a[2][v];
+          const C g8 = bit_l(v) ? w8 : a8;
+          const C g4 = ((sbits >> v) & 1u) ? w4 : a4;
+          const C g7 = bit_r(v) ? w7 : a7;
+          finish<C>(row_sum(g5, g2, g6), row_dif(g5, g6), row_sum(g1, g0, g3), row_dif(g1, g3),
+                    row_sum(g8, g4, g7), row_dif(g8, g7), dn, jxn, jyn);
+        } else {
+          finish<C>(up_old.s[v], up_old.x[v], lev.s[v], lev.x[v], row_sum(a8, a4, a7),
+                    row_dif(a8, a7), dn, jxn, jyn);
+        }
+        if (T::kScaled) {
+          dn *= ed;
+          jxn *= ej;
+          jyn *= ej;
+        }
+        S e0 = T::enc(dn), e1 = T::enc(jxn), e2 = T::enc(jyn);
+        if (HASWALL && !((own_fluid >> v) & 1u)) {
+          e0 = own_raw[0].v[v];
+          e1 = own_raw[1].v[v];
+          e2 = own_raw[2].v[v];
+        }
+        out[0].v[v] = e0;
+        out[1].v[v] = e1;
+        out[2].v[v] = e2;
+      }
+      if (t < ny && lane_ok) {
+        const long idx = (long)t * pitch + xc;
+        *reinterpret_cast<SP *>(d0p + idx) = out[0];
+        *reinterpret_cast<SP *>(d1p + idx) = out[1];
+        *reinterpret_cast<SP *>(d2p + idx) = out[2];
+      }
+    }
+
+    // ---- arrivals of this row for targets in rows r + 1 (into up_old) and r (into lev)
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) {
+      const C a5 = v > 0 ? f[v - 1][5] : L5;
+      const C a2 = f[v][2];
+      const C a6 = v < VEC - 1 ? f[v + 1][6] : R6;
+      const C a1 = v > 0 ? f[v - 1][1] : L1;
+      const C a0 = f[v][0];
+      const C a3 = v < VEC - 1 ? f[v + 1][3] : R3;
+      if constexpr (HASWALL) {
+        up_old.a[0][v] = a5;
+        up_old.a[1][v] = a2;
+        up_old.a[2][v] = a6;
+        lev.a[0][v] = a1;
+        lev.a[1][v] = a0;
+        lev.a[2][v] = a3;
+      } else {
+        up_old.s[v] = row_sum(a5, a2, a6);
+        up_old.x[v] = row_dif(a5, a6);
+        lev.s[v] = row_sum(a1, a0, a3);
+        lev.x[v] = row_dif(a1, a3);
+      }
+    }
+    if constexpr (HASWALL) {
+      uint32_t sb = 0;
+#pragma unroll
+      for (int v = 0; v < VEC; ++v)
+        sb |= (bit_l(v) | (((sbits >> v) & 1u) << 1) | (bit_r(v) << 2)) << (3 * v);
+      up_old.sb = sb;
+      lev.sb = sb;
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) {
+        own_d[v] = dd[v];
+        if constexpr (WALL == WALL_HALFWAY) {
+#pragma unroll
+          for (int q = 1; q < 9; ++q) own_f[q][v] = f[v][q];
+        }
+      }
+      own_fluid = fbits;
+      own_raw[0] = raw[0];
+      own_raw[1] = raw[1];
+      own_raw[2] = raw[2];
+    }
+  };
+
+  for (int i = 0; i < NY + 2; i += 2) {
+    body(i, upA);
+    body(i + 1, upB);
+  }
+}
+
+template <int P, bool HASWALL, int WALL, int VEC, int NY>
+__global__ void __launch_bounds__(256) k_step_strip(StepArgs a, StripMap m) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int xcd = blockIdx.x & 7;
+  const int local = blockIdx.x >> 3;
+  const int begin = xcd * m.per_xcd;
+  const int end = min(m.units, begin + m.per_xcd);
+  const int stride = m.persistent ? (int)(gridDim.x >> 3) : m.units;
+  for (int u = begin + local; u < end; u += stride) {
+    const int s = u * 4 + wave;  // strips ordered down each column band
+    const int sx = s / m.strips_y;
+    const int sy = s - sx * m.strips_y;
+    if (sx < m.strips_x) strip_body<P, HASWALL, WALL, VEC, NY>(a, sx * 64 * VEC, sy * NY, lane);
+  }
+}
+
+// ================================================================ reductions
+
+// out slots: 0 sum d, 1 sum jx, 2 sum jy, 3 max residual, 4 non-finite, 5 fluid count
+template <int P>
+__global__ void __launch_bounds__(256) k_reduce_partial(ReduceArgs a) {
+  using T = Traits<P>;
+  using S = typename T::S;
+  const S *c0 = static_cast<const S *>(a.cur[0]);
+  const S *c1 = static_cast<const S *>(a.cur[1]);
+  const S *c2 = static_cast<const S *>(a.cur[2]);
+  S *n0 = static_cast<S *>(a.snap[0]);
+  S *n1 = static_cast<S *>(a.snap[1]);
+  S *n2 = static_cast<S *>(a.snap[2]);
+  const bool want_res = a.what & 4u;
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  const long n = (long)a.nx * a.ny;
+  for (long k = (long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x) {
+    const int y = (int)(k / a.nx);
+    const int x = (int)(k - (long)y * a.nx);
+    const long i = (long)y * a.pitch + x;
+    if (a.flags && a.flags[i] != NODE_FLUID) continue;
+    const S r0 = c0[i], r1 = c1[i], r2 = c2[i];
+    const double d = (double)T::dec(r0) * a.sc_d;
+    const double jx = (double)T::dec(r1) * a.sc_j;
+    const double jy = (double)T::dec(r2) * a.sc_j;
+    acc[0] += d;
+    acc[1] += jx;
+    acc[2] += jy;
+    acc[4] += (__builtin_isfinite(d) && __builtin_isfinite(jx) && __builtin_isfinite(jy)) ? 0.0 : 1.0;
+    acc[5] += 1.0;
+    if (want_res) {
+      const double rho = 1.0 + d;
+      const double sr = 1.0 + (double)T::dec(n0[i]) * a.sc_d;
+      const double su = (double)T::dec(n1[i]) * a.sc_j / sr;
+      const double sv = (double)T::dec(n2[i]) * a.sc_j / sr;
+      const double du = __builtin_fabs(jx / rho - su);
+      const double dv = __builtin_fabs(jy / rho - sv);
+      acc[3] = __builtin_fmax(acc[3], __builtin_fmax(du, dv));
+      n0[i] = r0;
+      n1[i] = r1;
+      n2[i] = r2;
+    }
+  }
+  // wavefront tree (fixed order), then the four waves of the block in order
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      const double o = __shfl_xor(acc[q], off);
+      acc[q] = q == 3 ? __builtin_fmax(acc[q], o) : acc[q] + o;
+    }
+  }
+  __shared__ double part[4][6];
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int q = 0; q < 6; ++q) part[wave][q] = acc[q];
+  }
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    const int q = threadIdx.x;
+    double v = part[0][q];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w)
+      v = q == 3 ? __builtin_fmax(v, part[w][q]) : v + part[w][q];
+    a.partials[blockIdx.x * 6 + q] = v;
+  }
+}
+
+
+}  // namespace lbt1
+
+namespace lbt1 {
+
+// ================================================================ batched step
+
+
+// One wavefront per work item, grid-stride over all items of every grid with
+// columns per lane VEC.  Always takes the wall-aware path: on a grid with no
+// walls it gives the same bits as the wall-free kernels.
+template <int P, int VEC, int NY>
+__global__ void __launch_bounds__(256) k_step_batch(BatchStepArgs b) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int n = *b.count;
+  for (int it = blockIdx.x * 4 + wave; it < n; it += gridDim.x * 4) {
+    const int2 item = b.items[it];
+    const BatchGrid &g = b.grids[item.x];
+    if (b.step >= g.steps_left) continue;
+    const int p = (g.parity0 + b.step) & 1;
+    StepArgs a;
+    for (int q = 0; q < 3; ++q) {
+      a.src[q] = g.plane[p][q];
+      a.dst[q] = g.plane[1 - p][q];
+    }
+    a.flags = g.flags;
+    a.nx = g.nx;
+    a.ny = g.ny;
+    a.pitch = g.pitch;
+    a.periodic = g.periodic;
+    a.fx = g.fx;
+    a.fy = g.fy;
+    a.sc_d = g.sc_d;
+    a.sc_j = g.sc_j;
+    a.is_d = g.is_d;
+    a.is_j = g.is_j;
+    const int sx = item.y / g.strips_y;
+    const int sy = item.y - sx * g.strips_y;
+    if (g.wall == WALL_PAPER)
+      strip_body<P, true, WALL_PAPER, VEC, NY>(a, sx * 64 * VEC, sy * NY, lane);
+    else
+      strip_body<P, true, WALL_HALFWAY, VEC, NY>(a, sx * 64 * VEC, sy * NY, lane);
+  }
+}
+
+
+template <int P>
+__global__ void __launch_bounds__(256) k_reduce_batch(BatchReduceArgs b) {
+  using T = Traits<P>;
+  using S = typename T::S;
+  const int n = *b.nactive;
+  __shared__ double part[4][6];
+  for (int k = blockIdx.x; k < n; k += gridDim.x) {
+    const int slot = b.active[k];
+    const BatchGrid &g = b.grids[slot];
+    const int p = (g.parity0 + g.steps_left) & 1;
+    const S *c0 = static_cast<const S *>(g.plane[p][0]);
+    const S *c1 = static_cast<const S *>(g.plane[p][1]);
+    const S *c2 = static_cast<const S *>(g.plane[p][2]);
+    S *n0 = static_cast<S *>(b.snaps[slot * 3 + 0]);
+    S *n1 = static_cast<S *>(b.snaps[slot * 3 + 1]);
+    S *n2 = static_cast<S *>(b.snaps[slot * 3 + 2]);
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    const long nn = (long)g.nx * g.ny;
+    for (long m = threadIdx.x; m < nn; m += blockDim.x) {
+      const int y = (int)(m / g.nx);
+      const int x = (int)(m - (long)y * g.nx);
+      const long i = (long)y * g.pitch + x;
+      if (g.flags[i] != NODE_FLUID) continue;
+      const S r0 = c0[i], r1 = c1[i], r2 = c2[i];
+      const double d = (double)T::dec(r0) * g.sc_d;
+      const double jx = (double)T::dec(r1) * g.sc_j;
+      const double jy = (double)T::dec(r2) * g.sc_j;
+      acc[0] += d;
+      acc[1] += jx;
+      acc[2] += jy;
+      acc[4] += (__builtin_isfinite(d) && __builtin_isfinite(jx) && __builtin_isfinite(jy)) ? 0.0 : 1.0;
+      acc[5] += 1.0;
+      const double rho = 1.0 + d;
+      const double sr = 1.0 + (double)T::dec(n0[i]) * g.sc_d;
+      const double su = (double)T::dec(n1[i]) * g.sc_j / sr;
+      const double sv = (double)T::dec(n2[i]) * g.sc_j / sr;
+      acc[3] = __builtin_fmax(acc[3], __builtin_fmax(__builtin_fabs(jx / rho - su), __builtin_fabs(jy / rho - sv)));
+      n0[i] = r0;
+      n1[i] = r1;
+      n2[i] = r2;
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+#pragma unroll
+      for (int q = 0; q < 6; ++q) {
+        const double o = __shfl_xor(acc[q], off);
+        acc[q] = q == 3 ? __builtin_fmax(acc[q], o) : acc[q] + o;
+      }
+    }
+    const int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+      for (int q = 0; q < 6; ++q) part[wave][q] = acc[q];
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+      const int q = threadIdx.x;
+      double v = part[0][q];
+      for (int w = 1; w < (int)(blockDim.x >> 6); ++w) v = q == 3 ? __builtin_fmax(v, part[w][q]) : v + part[w][q];
+      b.out[slot * 6 + q] = v;
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace lbt1

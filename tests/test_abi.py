@@ -1,0 +1,74 @@
+"""The C-ABI library loads and exports what include/lbt1.h declares (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lbt1.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbt1_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1912_09327_amd import _capi as C
+    names = _declared()
+    assert len(names) >= 19
+    lib = ctypes.CDLL(C.LIB_PATH)
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    # the binding wraps exactly the declared calls
+    assert sorted(C.SIGNATURES) == names
+
+
+def test_grid_bytes_is_two_parities_of_three_planes_plus_flags():
+    """Eq. LBMTau1memory: 2 N_f c bytes per node of state (N_f = 3), on padded rows."""
+    from paper_1912_09327_amd import _capi as C
+    for prec, c in ((C.F64, 8), (C.F32, 4), (C.F16S, 2), (C.BF16S, 2)):
+        for nx, ny in ((64, 32), (1000, 1000), (8192, 8192), (37, 5)):
+            pitch = (nx + 63) // 64 * 64
+            plane = -(-pitch * ny * c // 256) * 256
+            flags = -(-pitch * ny // 256) * 256
+            base = C.grid_bytes(nx, ny, prec, 0)
+            assert base >= 6 * plane + flags
+            assert base - (6 * plane + flags) <= 64 * 1024          # reduction workspace only
+            assert C.grid_bytes(nx, ny, prec, C.OPT_SNAPSHOT) == base + 3 * plane
+    # the paper's 1000 x 1000 float example: 24 bytes per node of moments; rows
+    # padded to 1024 values here
+    assert 6 * 4 * 1024 * 1000 <= C.grid_bytes(1000, 1000, C.F32, 0) < 6 * 4 * 1024 * 1000 + 1_200_000
+
+
+def test_bad_arguments_are_rejected_before_any_device_work():
+    from paper_1912_09327_amd import _capi as C
+    assert C.grid_bytes(2, 10, C.F32) == 0
+    assert C.grid_bytes(10, 10, 7) == 0
+    d = C.GridDesc()
+    d.nx, d.ny, d.prec = 2, 10, C.F32
+    h = ctypes.c_void_p()
+    assert C.lib.lbt1_create_grid(ctypes.byref(d), ctypes.byref(h)) == C.EINVAL
+    assert b"each side" in C.lib.lbt1_last_error()
+    d.nx, d.ny, d.wall = 16, 16, 5
+    assert C.lib.lbt1_create_grid(ctypes.byref(d), ctypes.byref(h)) == C.EINVAL
+    d.wall = 0
+    d.scale[0] = 3.0
+    d.prec = C.F16S
+    assert C.lib.lbt1_create_grid(ctypes.byref(d), ctypes.byref(h)) == C.EINVAL
+    assert C.lib.lbt1_step(None, 1) == C.EINVAL
+    assert C.lib.lbt1_destroy_grid(None) == C.OK
+
+
+def test_no_cpu_fallback_without_a_device():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is visible")
+    from paper_1912_09327_amd import _capi as C
+    d = C.GridDesc()
+    d.nx, d.ny, d.prec = 16, 16, C.F32
+    h = ctypes.c_void_p()
+    assert C.lib.lbt1_create_grid(ctypes.byref(d), ctypes.byref(h)) == C.EDEVICE
+    assert b"device" in C.lib.lbt1_last_error()
