@@ -1,0 +1,261 @@
+#!/usr/bin/env python3
+"""Benchmark of the LBMTau1 D2Q9 step on one MI355X.
+
+Default workload: the 8192 x 8192 fully periodic random field (rho = 1 +
+1e-3 N(0,1), u = 0.01 N(0,1), seed 0), FP32 moment storage, the roofline run.
+A "step" is one LBMTau1 time step of the whole grid (gather of the nine
+upwind neighbours' moments, equilibria, sums, store), with the FP64
+mass / residual / non-finite reduction every 100 steps and the steps issued as
+HIP-graph bursts.  Inputs are resident in HBM before the timed region.
+
+The JSON line carries:
+  value        fluid lattice updates per second (MLUPS), whole job
+  roofline     the step kernel's algorithmic HBM bytes per launch (read and write
+               3 moment planes: 2 * 3 * c bytes per fluid node) over its average
+               launch duration from HIP events on the grid's stream, against 8 TB/s
+  cpu_baseline the FP64 CPU oracle on a bounded sample of the same workload
+  variants     the same run with FP64, FP16 and BF16 shifted storage, each with its
+               error against the FP64 run
+
+Other workloads: --workload cavities (batched uneven cavities vs one grid per
+launch), --workload serve (continuous-batching server vs FIFO); each prints its
+own line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+METRIC = "MLUPS + % HBM roofline (LBMTau1 D2Q9); batched p50/p99 vs plain per-grid"
+VALUE_BYTES = {"f64": 8, "f32": 4, "f16s": 2, "bf16s": 2}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=1000)
+    p.add_argument("--warmup", type=int, default=100)
+    p.add_argument("--workload", default="periodic", choices=["periodic", "cavities", "serve"])
+    p.add_argument("--n", type=int, default=8192, help="grid side of the periodic workload")
+    p.add_argument("--storage", default="f32", choices=["f64", "f32", "f16s", "bf16s"])
+    p.add_argument("--no-variants", action="store_true", help="skip the other storage variants")
+    p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    p.add_argument("--no-tune", action="store_true", help="skip the autotuner")
+    p.add_argument("--kernel", default=None, help="fix the kernel: gather or strip:vec:rows:waves")
+    p.add_argument("--planar", action="store_true", help="three separate moment planes instead of "
+                   "the row-interleaved layout")
+    p.add_argument("--cpu-seconds", type=float, default=12.0)
+    p.add_argument("--cavities", type=int, default=512)
+    p.add_argument("--max-steps", type=int, default=200000)
+    p.add_argument("--requests", type=int, default=200)
+    p.add_argument("--load", type=float, default=0.7)
+    return p.parse_args()
+
+
+# ------------------------------------------------------------------ periodic roofline run
+def make_grid(n, storage, state, tune=True, kernel=None, planar=False):
+    from paper_1912_09327_amd.grid import Grid
+    g = Grid(n, n, prec=storage, periodic=3, planar=planar)
+    g.set_geometry(None, *state)
+    if kernel:
+        if kernel == "gather":
+            g.set_kernel("gather")
+        else:
+            _, v, r, w = kernel.split(":")
+            g.set_kernel("strip", int(v), int(r), int(w))
+    elif tune:
+        g.autotune(steps=10, reps=2)
+    return g
+
+
+def timed_run(g, steps, warmup, torch):
+    """Warm up, then time exactly `steps` steps: reductions every 100 steps, HIP events
+    around every block of step launches on the grid's stream."""
+    s = g.stream
+    g.step(warmup)
+    g.reduce()
+    torch.cuda.synchronize()
+    ev = []
+    t0 = time.perf_counter()
+    done = 0
+    while done < steps:
+        k = min(100, steps - done)
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(s)
+        g.step(k)
+        b.record(s)
+        ev.append((a, b, k))
+        done += k
+        if done % 100 == 0 or done == steps:
+            g.reduce()                   # FP64 mass / residual / non-finite, synchronises
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern_ms = sum(a.elapsed_time(b) for a, b, _ in ev)
+    return wall, kern_ms / steps
+
+
+def copy_ceiling(torch, nbytes=2 << 30):
+    """Achievable HBM bandwidth of a plain device copy (read + write) on this GPU."""
+    x = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    x.fill_(1.0)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    reps = 10
+    a.record()
+    for _ in range(reps):
+        y.copy_(x)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    del x, y
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
+def cpu_baseline(state, budget_s):
+    """The FP64 oracle on a 2048 x 2048 window of the same random field, OpenMP over rows."""
+    import oracle
+    threads = len(os.sched_getaffinity(0))
+    oracle.set_threads(threads)
+    m = min(2048, state[0].shape[0])
+    sub = [np.ascontiguousarray(a[:m, :m]) for a in state]
+    t0 = time.perf_counter()
+    oracle.run(*sub, 1, None, 3)
+    one = time.perf_counter() - t0
+    n = max(1, int(budget_s / max(one, 1e-3)))
+    t0 = time.perf_counter()
+    oracle.run(*sub, n, None, 3)
+    dt = time.perf_counter() - t0
+    return dict(value=round(m * m * n / dt / 1e6, 2), unit="MLUPS", cores=threads, kind="oracle",
+                sample=f"{m}x{m} periodic window of the same seed-0 random field, {n} steps, "
+                       f"FP64, {threads} OpenMP threads, {dt:.1f} s")
+
+
+def field_error(a, ref):
+    """Max and rms difference of (rho, jx, jy) against the FP64 run, normalised by the
+    FP64 field's rms (the random field decays, so absolute errors mislead)."""
+    out = {}
+    for name, x, r in zip(("rho", "jx", "jy"), a, ref):
+        if name == "rho":
+            x, r = x - 1.0, r - 1.0
+        rms = float(np.sqrt(np.mean(r * r)))
+        d = x - r
+        out[name] = dict(max=float(np.abs(d).max() / rms), rms=float(np.sqrt(np.mean(d * d)) / rms))
+    return out
+
+
+def run_periodic(args, torch):
+    from paper_1912_09327_amd import inputs as I
+    n = args.n
+    log(f"[bench] generating the {n}x{n} periodic field (seed 0)")
+    state = I.random_periodic(n, n, seed=0)
+    lups = float(n) * n
+    results = {}
+    order = [args.storage] + ([] if args.no_variants else
+                              [s for s in ("f64", "f32", "f16s", "bf16s") if s != args.storage])
+    ref_fields = None
+    fields = {}
+    for storage in order:
+        log(f"[bench] {storage}: set_geometry + autotune")
+        g = make_grid(n, storage, state, tune=not args.no_tune, kernel=args.kernel, planar=args.planar)
+        cfg, kname = g.kernel()
+        log(f"[bench] {storage}: kernel {kname} {cfg}")
+        wall, kms = timed_run(g, args.steps, args.warmup, torch)
+        c = VALUE_BYTES[storage]
+        achieved = 2 * 3 * c * lups / (kms * 1e-3) / 1e9
+        results[storage] = dict(mlups=lups * args.steps / wall / 1e6, ms_per_step=wall * 1e3 / args.steps,
+                                kernel_ms=kms, achieved=achieved, kernel=kname, config=cfg)
+        log(f"[bench] {storage}: {results[storage]['mlups']:.0f} MLUPS, kernel {kms:.4f} ms, "
+            f"{achieved:.0f} GB/s")
+        if not args.no_variants:
+            # every variant has now taken warmup + steps steps from the same start
+            fields[storage] = g.read_moments()
+        g.close()
+        torch.cuda.empty_cache()
+    if "f64" in fields:
+        ref_fields = fields["f64"]
+    head = results[args.storage]
+    c = VALUE_BYTES[args.storage]
+    line = {
+        "metric": METRIC,
+        "value": round(head["mlups"], 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(head["ms_per_step"], 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.storage == "f64" else "f32",
+        "data": "synthetic",
+        "config": {"workload": f"periodic {n}x{n} random field (rho = 1 + 1e-3 N(0,1), "
+                               f"u = 0.01 N(0,1), seed 0), {args.storage} moment storage",
+                   "nx": n, "ny": n, "storage": args.storage, "fluid_nodes": int(lups),
+                   "reduction_every": 100, "kernel": head["kernel"], "kernel_config": head["config"]},
+        "roofline": {"bound": "hbm", "achieved": round(head["achieved"], 1), "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": round(head["achieved"] / HBM_PEAK_GBPS, 4), "traffic": None,
+                     "bytes_per_lup": 2 * 3 * c, "kernel_ms": round(head["kernel_ms"], 5)},
+    }
+    try:
+        cc = copy_ceiling(torch)
+        line["roofline"]["copy_ceiling_GBps"] = round(cc, 1)
+        line["roofline"]["frac_of_copy"] = round(head["achieved"] / cc, 4)
+    except Exception as e:  # pragma: no cover - measurement aid only
+        log(f"[bench] copy ceiling failed: {e}")
+    if not args.no_variants:
+        var = {}
+        for s, r in results.items():
+            v = dict(mlups=round(r["mlups"], 1), achieved_GBps=round(r["achieved"], 1),
+                     frac=round(r["achieved"] / HBM_PEAK_GBPS, 4), kernel=r["kernel"])
+            if ref_fields is not None and s != "f64":
+                v["error_vs_f64"] = field_error(fields[s], ref_fields)
+                v["error_vs_f64"]["after_steps"] = args.warmup + args.steps
+            var[s] = v
+        line["variants"] = var
+    if not args.no_cpu:
+        log("[bench] CPU oracle baseline")
+        line["cpu_baseline"] = cpu_baseline(state, args.cpu_seconds)
+    return line
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(independent grids would shard across GPUs with no exchange; see the design notes)",
+              file=sys.stderr)
+        return 2
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        return 1
+    if args.workload == "periodic":
+        line = run_periodic(args, torch)
+    elif args.workload == "cavities":
+        from paper_1912_09327_amd.workloads import bench_cavities
+        line = bench_cavities(args, torch, log)
+    else:
+        from paper_1912_09327_amd.workloads import bench_serve
+        line = bench_serve(args, torch, log)
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

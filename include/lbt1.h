@@ -83,7 +83,13 @@ enum {
 enum { LBT1_PERIODIC_X = 1u, LBT1_PERIODIC_Y = 2u };
 
 /* lbt1_grid_desc.options bits */
-enum { LBT1_OPT_SNAPSHOT = 1u /* keep a copy of the state for the residual */ };
+enum {
+  LBT1_OPT_SNAPSHOT = 1u, /* keep a copy of the state for the residual */
+  LBT1_OPT_PLANAR = 2u    /* store rho - 1, jx, jy as three separate planes; by default
+                             the three rows of each lattice row are adjacent in memory
+                             ([ny][3][pitch]), so a row is one contiguous read and one
+                             contiguous write */
+};
 
 /* lbt1_reduce what-mask bits and output slots */
 enum {
@@ -115,10 +121,11 @@ typedef struct {
   void *stream;          /* hipStream_t to run on; NULL: a library-owned stream */
 } lbt1_grid_desc;
 
-/* Device bytes a grid of this shape needs: two parities of three moment
- * planes (the paper's 2 N_f c per node, Eq. LBMTau1memory, with rows padded
- * to 64 values), one flag byte per node, three more planes with
- * LBT1_OPT_SNAPSHOT, and a small reduction workspace.  0 on bad arguments. */
+/* Device bytes a grid of this shape needs: two parities of the three moment
+ * fields (the paper's 2 N_f c per node, Eq. LBMTau1memory, with rows padded
+ * to 64 values), one flag byte per node, one more copy of the three fields
+ * with LBT1_OPT_SNAPSHOT, and a small reduction workspace.  0 on bad
+ * arguments. */
 size_t lbt1_grid_bytes(int32_t nx, int32_t ny, int32_t prec, uint32_t options);
 
 /* Create a grid (no device work yet besides allocation).  *out receives the handle. */
@@ -237,6 +244,25 @@ lbt1_status lbt1_batch_evict(lbt1_batch *b, int32_t slot);
 
 /* Release the batch (it must be empty or its grids are simply evicted). */
 lbt1_status lbt1_batch_destroy(lbt1_batch *b);
+
+/* ---------------------------------------------------------------- diagnostics */
+
+enum {
+  LBT1_PROBE_COPY = 0,     /* one input stream, one output stream */
+  LBT1_PROBE_READ = 1,     /* one input stream */
+  LBT1_PROBE_WRITE = 2,    /* one output stream */
+  LBT1_PROBE_3IN3OUT = 3   /* three inputs, three outputs: the access pattern of one
+                              moments-only step over three moment planes */
+};
+
+/* Achievable device bandwidth of a plain streaming pattern: library-allocated
+ * scratch of about `bytes` bytes (>= 1 MiB) split over the pattern's streams,
+ * float4 accesses, stores nontemporal when `nontemporal` != 0.  Eight launch
+ * shapes are tried (4 to 32 blocks of 256 threads per CU, one or several
+ * elements in flight per thread), each `reps` timed launches after a warm-up;
+ * *gbps = bytes read and written / time of the fastest, in GB/s.  Runs on the
+ * current device's null stream and synchronises. */
+lbt1_status lbt1_probe_bandwidth(int32_t kind, size_t bytes, int32_t nontemporal, int32_t reps, double *gbps);
 
 #ifdef __cplusplus
 }

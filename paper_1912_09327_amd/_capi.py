@@ -24,11 +24,13 @@ WALLS = {"paper": WALL_PAPER, "halfway": WALL_HALFWAY}
 FLUID, SOLID, FIXED = 0, 1, 2
 PERIODIC_X, PERIODIC_Y = 1, 2
 OPT_SNAPSHOT = 1
+OPT_PLANAR = 2
 REDUCE_MASS, REDUCE_MOMENTUM, REDUCE_RESIDUAL, REDUCE_NONFINITE = 1, 2, 4, 8
 REDUCE_ALL = 15
 REDUCE_SLOTS = 6
 KERNEL_AUTO, KERNEL_GATHER, KERNEL_STRIP = 0, 1, 2
 SLOT_FREE, SLOT_RUNNING, SLOT_BUDGET, SLOT_CONVERGED, SLOT_NONFINITE = range(5)
+PROBE_COPY, PROBE_READ, PROBE_WRITE, PROBE_3IN3OUT = range(4)
 
 
 class Lbt1Error(RuntimeError):
@@ -82,6 +84,7 @@ SIGNATURES = {
     "lbt1_batch_slot_info": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(_i32), ctypes.POINTER(ctypes.c_int64), _dp]),
     "lbt1_batch_evict": (ctypes.c_int, [_vp, _i32]),
     "lbt1_batch_destroy": (ctypes.c_int, [_vp]),
+    "lbt1_probe_bandwidth": (ctypes.c_int, [_i32, ctypes.c_size_t, _i32, _i32, _dp]),
 }
 
 
@@ -114,3 +117,10 @@ def check(status):
 
 def grid_bytes(nx, ny, prec, options=OPT_SNAPSHOT):
     return int(lib.lbt1_grid_bytes(int(nx), int(ny), int(prec), int(options)))
+
+
+def probe_bandwidth(kind, nbytes=4 << 30, nontemporal=False, reps=5):
+    """Achievable GB/s of a plain streaming pattern (PROBE_*) on the current device."""
+    out = ctypes.c_double()
+    check(lib.lbt1_probe_bandwidth(int(kind), int(nbytes), int(bool(nontemporal)), int(reps), ctypes.byref(out)))
+    return out.value

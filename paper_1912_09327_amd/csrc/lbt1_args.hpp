@@ -9,7 +9,7 @@ namespace lbt1 {
 
 struct StripMap {
   int strips_x, strips_y;  // strips per row band / per column band
-  int units;               // groups of 4 vertically adjacent strips (one per block)
+  int units;               // groups of 4 consecutive strips (one per block)
   int per_xcd;             // units per XCD range
   int persistent;          // 0: one block per unit; else grid-stride within the XCD range
 };
@@ -18,7 +18,7 @@ struct ReduceArgs {
   const void *cur[3];
   void *snap[3];
   const uint8_t *flags;  // NULL: every node FLUID
-  int nx, ny, pitch;
+  int nx, ny, pitch, rs; // flag / moment row strides in values
   double sc_d, sc_j;
   uint32_t what;         // LBT1_REDUCE_* bits
   double *partials;      // 6 per block
@@ -30,18 +30,19 @@ struct ReduceArgs {
 struct BatchGrid {
   void *plane[2][3];
   const uint8_t *flags;
-  int nx, ny, pitch;
+  int nx, ny, pitch, rs;  // flag / moment row strides in values
   uint32_t periodic;
   int wall;
   int parity0;
   int steps_left;
-  int strips_y;
+  int strips_x;  // strips per row band (columns of 64 * vec)
   double fx, fy, sc_d, sc_j, is_d, is_j;
+  void *trash;  // see StepArgs::trash
 };
 
 struct BatchStepArgs {
   const BatchGrid *grids;
-  const int2 *items;  // (slot, strip index), strips ordered down each column band
+  const int2 *items;  // (slot, strip index), strips ordered along each row band
   const int *count;   // number of items (device memory, so a graph need not change)
   int step;           // step index inside the burst
 };

@@ -267,17 +267,19 @@ lbt1_status lbt1_batch_admit(lbt1_batch *b, lbt1_grid *g, int64_t step_budget, d
   d.nx = g->nx;
   d.ny = g->ny;
   d.pitch = g->L.pitch;
+  d.rs = g->L.rs;
   d.periodic = g->periodic;
   d.wall = g->wall;
   d.parity0 = g->parity;
   d.steps_left = 0;
-  d.strips_y = (g->ny + 13) / 14;
+  d.strips_x = (g->nx + 64 * kVecOfClass[sl.vclass] - 1) / (64 * kVecOfClass[sl.vclass]);
   d.fx = g->F[0];
   d.fy = g->F[1];
   d.sc_d = g->sc[0];
   d.sc_j = g->sc[1];
   d.is_d = 1.0 / g->sc[0];
   d.is_j = 1.0 / g->sc[1];
+  d.trash = g->base + g->L.trash_off;
   for (int q = 0; q < 3; ++q) b->h_snaps[3 * s + q] = g->snap[q];
   b->items_dirty = true;
   *slot = s;

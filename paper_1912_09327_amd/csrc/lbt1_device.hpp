@@ -130,11 +130,16 @@ struct StepArgs {
   const void *src[3];  // d, jx, jy planes of the current parity
   void *dst[3];        // planes of the next parity
   const uint8_t *flags;
-  int nx, ny, pitch;   // pitch in values (a multiple of 64)
+  int nx, ny;
+  int pitch;           // flag row stride in values (nx rounded up to 64)
+  int rs;              // moment row stride in values (pitch, or 3 * pitch when the
+                       // three moment rows of a lattice row are adjacent)
   uint32_t periodic;   // bit 0 x, bit 1 y
   double fx, fy;       // body force
   double sc_d, sc_j;   // decode scales (stored * sc = value)
   double is_d, is_j;   // encode scales (value * is = stored)
+  void *trash;         // 3 KiB of device scratch: target of the stores of lanes and
+                       // rows outside the grid, so that stores need no branch
 };
 
 // Source coordinate along one axis: wrapped when periodic, -1 when outside.

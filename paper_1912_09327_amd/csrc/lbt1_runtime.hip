@@ -63,13 +63,26 @@ Layout layout_of(int nx, int ny, int prec, uint32_t options) {
   Layout L{};
   const size_t c = value_bytes(prec);
   L.pitch = (int)round_up((size_t)nx, 64);
-  L.plane = round_up((size_t)L.pitch * ny * c, 256);
-  L.flags_off = 6 * L.plane;
+  L.interleaved = !(options & LBT1_OPT_PLANAR);
+  if (L.interleaved) {
+    // [ny][3][pitch]: a wavefront reading (writing) one lattice row touches one
+    // contiguous stretch of the parity block
+    L.rs = 3 * L.pitch;
+    for (int q = 0; q < 3; ++q) L.field_off[q] = (size_t)q * L.pitch * c;
+    L.state = round_up((size_t)3 * L.pitch * ny * c, 256);
+  } else {
+    // [3][ny][pitch]: three separate planes
+    const size_t plane = round_up((size_t)L.pitch * ny * c, 256);
+    L.rs = L.pitch;
+    for (int q = 0; q < 3; ++q) L.field_off[q] = (size_t)q * plane;
+    L.state = 3 * plane;
+  }
+  L.flags_off = 2 * L.state;
   L.flags_bytes = round_up((size_t)L.pitch * ny, 256);
   size_t off = L.flags_off + L.flags_bytes;
   if (options & LBT1_OPT_SNAPSHOT) {
     L.snap_off = off;
-    off += 3 * L.plane;
+    off += L.state;
   } else {
     L.snap_off = 0;
   }
@@ -78,6 +91,8 @@ Layout layout_of(int nx, int ny, int prec, uint32_t options) {
   off += round_up((size_t)L.nparts * 6 * sizeof(double), 256);
   L.out_off = off;
   off += 256;
+  L.trash_off = off;  // 3 KiB: stores of lanes / rows outside the grid land here
+  off += 3 * 1024;
   L.total = off;
   return L;
 }
@@ -310,6 +325,7 @@ StepArgs step_args(const lbt1_grid *g, int src_parity) {
   a.nx = g->nx;
   a.ny = g->ny;
   a.pitch = g->L.pitch;
+  a.rs = g->L.rs;
   a.periodic = g->periodic;
   a.fx = g->F[0];
   a.fy = g->F[1];
@@ -317,6 +333,7 @@ StepArgs step_args(const lbt1_grid *g, int src_parity) {
   a.sc_j = g->sc[1];
   a.is_d = 1.0 / g->sc[0];
   a.is_j = 1.0 / g->sc[1];
+  a.trash = g->base + g->L.trash_off;
   return a;
 }
 
@@ -414,6 +431,7 @@ lbt1_status enqueue_reduce(lbt1_grid *g, uint32_t what, hipStream_t s) {
   a.nx = g->nx;
   a.ny = g->ny;
   a.pitch = g->L.pitch;
+  a.rs = g->L.rs;
   a.sc_d = g->sc[0];
   a.sc_j = g->sc[1];
   a.what = what;
@@ -454,7 +472,7 @@ lbt1_status lbt1_create_grid(const lbt1_grid_desc *d, lbt1_grid **out) {
   if (!valid_prec(d->prec)) return fail(LBT1_EINVAL, "unknown precision %d", d->prec);
   if (d->wall != LBT1_WALL_PAPER && d->wall != LBT1_WALL_HALFWAY) return fail(LBT1_EINVAL, "unknown wall rule %d", d->wall);
   if (d->periodic & ~3u) return fail(LBT1_EINVAL, "periodic mask %u", d->periodic);
-  if (d->options & ~(uint32_t)LBT1_OPT_SNAPSHOT) return fail(LBT1_EINVAL, "unknown options %u", d->options);
+  if (d->options & ~(uint32_t)(LBT1_OPT_SNAPSHOT | LBT1_OPT_PLANAR)) return fail(LBT1_EINVAL, "unknown options %u", d->options);
   if (!std::isfinite(d->force[0]) || !std::isfinite(d->force[1])) return fail(LBT1_EINVAL, "force must be finite");
   if (!pow2_or_zero(d->scale[0]) || !pow2_or_zero(d->scale[1]))
     return fail(LBT1_EINVAL, "scales must be 0 or positive powers of two");
@@ -510,9 +528,10 @@ lbt1_status lbt1_create_grid(const lbt1_grid_desc *d, lbt1_grid **out) {
     g->own_stream = true;
   }
   for (int p = 0; p < 2; ++p)
-    for (int q = 0; q < 3; ++q) g->plane[p][q] = g->base + (size_t)(3 * p + q) * g->L.plane;
+    for (int q = 0; q < 3; ++q) g->plane[p][q] = g->base + (size_t)p * g->L.state + g->L.field_off[q];
   g->flags = (uint8_t *)(g->base + g->L.flags_off);
-  for (int q = 0; q < 3; ++q) g->snap[q] = (d->options & LBT1_OPT_SNAPSHOT) ? g->base + g->L.snap_off + q * g->L.plane : nullptr;
+  for (int q = 0; q < 3; ++q)
+    g->snap[q] = (d->options & LBT1_OPT_SNAPSHOT) ? g->base + g->L.snap_off + g->L.field_off[q] : nullptr;
   g->partials = (double *)(g->base + g->L.part_off);
   g->red_out = (double *)(g->base + g->L.out_off);
   if ((e = hipHostMalloc((void **)&g->red_host, 8 * sizeof(double), hipHostMallocDefault)) != hipSuccess) {
@@ -560,7 +579,7 @@ lbt1_status lbt1_set_geometry(lbt1_grid *g, const uint8_t *flags, const double *
   std::vector<char> stage;
   std::vector<uint8_t> fstage;
   try {
-    stage.assign(3 * plane_vals * c, 0);
+    stage.assign(g->L.state, 0);
     fstage.assign(plane_vals, LBT1_SOLID);
   } catch (...) {
     return fail(LBT1_ENOMEM, "host staging");
@@ -574,7 +593,7 @@ lbt1_status lbt1_set_geometry(lbt1_grid *g, const uint8_t *flags, const double *
         row[x] = src ? (q == 0 ? src[i] - 1.0 : src[i]) : 0.0;
       }
       encode_values(g->prec, row.data(), nx, 1.0 / g->sc[q == 0 ? 0 : 1],
-                    stage.data() + (q * plane_vals + (size_t)y * pitch) * c);
+                    stage.data() + g->L.field_off[q] + (size_t)y * g->L.rs * c);
     }
     for (int x = 0; x < nx; ++x) fstage[(size_t)y * pitch + x] = flags ? flags[(size_t)y * nx + x] : LBT1_FLUID;
   }
@@ -582,12 +601,10 @@ lbt1_status lbt1_set_geometry(lbt1_grid *g, const uint8_t *flags, const double *
   if ((e = hipSetDevice(g->device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
   if ((e = hipStreamSynchronize(g->stream)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
   for (int p = 0; p < 2; ++p)
-    for (int q = 0; q < 3; ++q)
-      if ((e = hipMemcpy(g->plane[p][q], stage.data() + q * plane_vals * c, plane_vals * c, hipMemcpyHostToDevice)) != hipSuccess)
-        return hip_fail(e, "hipMemcpy H2D");
-  for (int q = 0; q < 3 && g->snap[0]; ++q)
-    if ((e = hipMemcpy(g->snap[q], stage.data() + q * plane_vals * c, plane_vals * c, hipMemcpyHostToDevice)) != hipSuccess)
+    if ((e = hipMemcpy(g->base + (size_t)p * g->L.state, stage.data(), g->L.state, hipMemcpyHostToDevice)) != hipSuccess)
       return hip_fail(e, "hipMemcpy H2D");
+  if (g->snap[0] && (e = hipMemcpy(g->base + g->L.snap_off, stage.data(), g->L.state, hipMemcpyHostToDevice)) != hipSuccess)
+    return hip_fail(e, "hipMemcpy H2D");
   if ((e = hipMemcpy(g->flags, fstage.data(), plane_vals, hipMemcpyHostToDevice)) != hipSuccess)
     return hip_fail(e, "hipMemcpy H2D");
   g->haswall = any_nonfluid || g->periodic != 3u;
@@ -640,7 +657,7 @@ lbt1_status lbt1_read_moments(lbt1_grid *g, double *rho, double *jx, double *jy)
   for (int q = 0; q < 3; ++q) {
     double *dst = q == 0 ? rho : q == 1 ? jx : jy;
     if (!dst) continue;
-    if ((e = hipMemcpy2D(stage.data(), (size_t)nx * c, g->plane[g->parity][q], (size_t)g->L.pitch * c, (size_t)nx * c, ny,
+    if ((e = hipMemcpy2D(stage.data(), (size_t)nx * c, g->plane[g->parity][q], (size_t)g->L.rs * c, (size_t)nx * c, ny,
                          hipMemcpyDeviceToHost)) != hipSuccess)
       return hip_fail(e, "hipMemcpy2D D2H");
     decode_values(g->prec, stage.data(), (size_t)nx * ny, g->sc[q == 0 ? 0 : 1], dst);
@@ -739,15 +756,15 @@ lbt1_status lbt1_autotune(lbt1_grid *g, int32_t steps, int32_t reps, lbt1_kernel
   t.burst[0] = t.burst[1] = nullptr;
   t.graph_valid = false;
   void *p = nullptr;
-  if ((e = hipMalloc(&p, 6 * g->L.plane + g->L.flags_bytes)) != hipSuccess)
+  // same layout as the grid (step_args derives the trash area from the base)
+  if ((e = hipMalloc(&p, g->L.total)) != hipSuccess)
     return fail(LBT1_ENOMEM, "autotune scratch: %s", hipGetErrorString(e));
   t.base = (char *)p;
   for (int a = 0; a < 2; ++a)
-    for (int q = 0; q < 3; ++q) t.plane[a][q] = t.base + (size_t)(3 * a + q) * g->L.plane;
-  t.flags = (uint8_t *)(t.base + 6 * g->L.plane);
-  for (int a = 0; a < 2; ++a)
-    for (int q = 0; q < 3; ++q) hipMemcpyAsync(t.plane[a][q], g->plane[a][q], g->L.plane, hipMemcpyDeviceToDevice, g->stream);
-  hipMemcpyAsync(t.flags, g->flags, g->L.flags_bytes, hipMemcpyDeviceToDevice, g->stream);
+    for (int q = 0; q < 3; ++q) t.plane[a][q] = t.base + (size_t)a * g->L.state + g->L.field_off[q];
+  t.flags = (uint8_t *)(t.base + g->L.flags_off);
+  (void)hipMemcpyAsync(t.base, g->base, 2 * g->L.state, hipMemcpyDeviceToDevice, g->stream);
+  (void)hipMemcpyAsync(t.flags, g->flags, g->L.flags_bytes, hipMemcpyDeviceToDevice, g->stream);
   hipEvent_t e0, e1;
   hipEventCreate(&e0);
   hipEventCreate(&e1);

@@ -13,12 +13,15 @@ namespace lbt1 {
 constexpr int kReduceBlocks = 1024;  // most partial rows a reduction writes
 
 struct Layout {
-  int pitch;          // values per row (nx rounded up to 64)
-  size_t plane;       // bytes per moment plane (256-byte multiple)
+  int pitch;          // values per row of one field (nx rounded up to 64)
+  int rs;             // moment row stride in values: pitch (planar) or 3 * pitch
+  bool interleaved;   // the three moment rows of a lattice row are adjacent
+  size_t field_off[3];  // byte offset of field q inside a parity block
+  size_t state;       // bytes of one parity block (three fields, 256-byte multiple)
   size_t flags_off, flags_bytes;
   size_t snap_off;    // 0 without LBT1_OPT_SNAPSHOT
   int nparts;
-  size_t part_off, out_off;
+  size_t part_off, out_off, trash_off;
   size_t total;
 };
 

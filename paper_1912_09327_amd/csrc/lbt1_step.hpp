@@ -43,8 +43,8 @@ __device__ __forceinline__ void gather_node(const StepArgs &a, int x, int y) {
   using T = Traits<P>;
   using C = typename T::C;
   using S = typename T::S;
-  const long i = (long)y * a.pitch + x;
-  if (HASWALL && a.flags[i] != NODE_FLUID) return;  // held in both parities
+  const long i = (long)y * a.rs + x;
+  if (HASWALL && a.flags[(long)y * a.pitch + x] != NODE_FLUID) return;  // held in both parities
   const C Fx = C(a.fx), Fy = C(a.fy);
   C d0, jx0, jy0;
   load_node<P>(a, i, d0, jx0, jy0);
@@ -57,8 +57,8 @@ __device__ __forceinline__ void gather_node(const StepArgs &a, int x, int y) {
     const int sx = wrap_axis(x - kEx[q], a.nx, a.periodic & 1u);
     const int sy = wrap_axis(y - kEy[q], a.ny, a.periodic & 2u);
     bool solid = (sx < 0) || (sy < 0);
-    const long s = solid ? 0 : (long)sy * a.pitch + sx;
-    if (HASWALL && !solid) solid = a.flags[s] == NODE_SOLID;
+    const long s = solid ? 0 : (long)sy * a.rs + sx;
+    if (HASWALL && !solid) solid = a.flags[(long)sy * a.pitch + sx] == NODE_SOLID;
     if (!solid) {
       C d, jx, jy;
       load_node<P>(a, s, d, jx, jy);
@@ -106,6 +106,9 @@ struct ArrS {  // the same arrivals already reduced (no walls): row sum and x di
 };
 
 
+// Rows whose loads are issued ahead of the row being computed.
+constexpr int kPrefetch = 2;
+
 template <int P, bool HASWALL, int WALL, int VEC, int NY>
 __device__ __forceinline__ void strip_body(const StepArgs &a, const int cx0, const int y0,
                                            const int lane) {
@@ -114,10 +117,10 @@ __device__ __forceinline__ void strip_body(const StepArgs &a, const int cx0, con
   using S = typename T::S;
   using SP = Pack<S, VEC>;
   using FP = Pack<uint8_t, VEC>;
-  static_assert(NY % 2 == 0 && NY + 2 <= 32, "strip height");
+  static_assert(NY + 2 <= 32, "strip height");
 
   const int nx = a.nx, ny = a.ny;
-  const long pitch = a.pitch;
+  const long pitch = a.pitch, rs = a.rs;
   const bool px = a.periodic & 1u, py = a.periodic & 2u;
   const C Fx = C(a.fx), Fy = C(a.fy);
   const C sd = C(a.sc_d), sj = C(a.sc_j), ed = C(a.is_d), ej = C(a.is_j);
@@ -144,8 +147,8 @@ __device__ __forceinline__ void strip_body(const StepArgs &a, const int cx0, con
       if (side == 1 && c >= nx) c = nx;
       c = wrap_axis(c, nx, px);
       if (r >= 0 && c >= 0) {
-        const long idx = (long)r * pitch + c;
-        if (!HASWALL || a.flags[idx] != NODE_SOLID) {
+        const long idx = (long)r * rs + c;
+        if (!HASWALL || a.flags[(long)r * pitch + c] != NODE_SOLID) {
           C d = T::dec(s0[idx]), jx = T::dec(s1[idx]), jy = T::dec(s2[idx]);
           if (T::kScaled) {
             d *= sd;
@@ -173,25 +176,37 @@ __device__ __forceinline__ void strip_body(const StepArgs &a, const int cx0, con
   (void)own_f;
   (void)own_fluid;
 
-  auto body = [&](const int i, Arr &up_old) __attribute__((always_inline)) {
-    const int r = y0 - 1 + i;
-    const int rr = wrap_axis(r, ny, py);
-    const bool row_ok = rr >= 0;
+  // Source row i of the strip (row y0 - 1 + i) in storage form; rows outside a
+  // non-periodic axis read as walls.
+  struct Row {
     SP raw[3];
     FP fl;
-    if (row_ok && lane_ok) {
-      const long idx = (long)rr * pitch + xc;
-      raw[0] = *reinterpret_cast<const SP *>(s0 + idx);
-      raw[1] = *reinterpret_cast<const SP *>(s1 + idx);
-      raw[2] = *reinterpret_cast<const SP *>(s2 + idx);
-      if (HASWALL) fl = *reinterpret_cast<const FP *>(a.flags + idx);
-    } else {
+  };
+  // The loads are unconditional (lanes past the grid's edge and rows outside a
+  // non-periodic axis read row 0 / column 0 instead and are then ignored or
+  // flagged as walls): with no branch around them the compiler keeps exact
+  // track of the loads in flight, which is what lets the prefetch overlap.
+  auto load_row = [&](const int i, Row &dst) __attribute__((always_inline)) {
+    const int rr = wrap_axis(y0 - 1 + i, ny, py);
+    const bool row_ok = rr >= 0;
+    const long row = row_ok ? rr : 0;
+    const long col = lane_ok ? xc : 0;
+    const long idx = row * rs + col;
+    dst.raw[0] = *reinterpret_cast<const SP *>(s0 + idx);
+    dst.raw[1] = *reinterpret_cast<const SP *>(s1 + idx);
+    dst.raw[2] = *reinterpret_cast<const SP *>(s2 + idx);
+    if (HASWALL) {
+      const FP f = *reinterpret_cast<const FP *>(a.flags + row * pitch + col);
 #pragma unroll
-      for (int v = 0; v < VEC; ++v) {
-        raw[0].v[v] = raw[1].v[v] = raw[2].v[v] = S(0);
-        fl.v[v] = row_ok ? NODE_FLUID : NODE_SOLID;
-      }
+      for (int v = 0; v < VEC; ++v) dst.fl.v[v] = row_ok ? f.v[v] : (uint8_t)NODE_SOLID;
     }
+  };
+
+  // Row i is processed while the loads of the following PF rows are in flight.
+  auto body = [&](const int i, Arr &up_old, const Row &cur) __attribute__((always_inline)) {
+    const int r = y0 - 1 + i;
+    const SP *raw = cur.raw;
+    const FP &fl = cur.fl;
     C f[VEC][9];
     C dd[VEC];
     uint32_t sbits = 0, fbits = 0;
@@ -303,11 +318,15 @@ __device__ __forceinline__ void strip_body(const StepArgs &a, const int cx0, con
         out[1].v[v] = e1;
         out[2].v[v] = e2;
       }
-      if (t < ny && lane_ok) {
-        const long idx = (long)t * pitch + xc;
-        *reinterpret_cast<SP *>(d0p + idx) = out[0];
-        *reinterpret_cast<SP *>(d1p + idx) = out[1];
-        *reinterpret_cast<SP *>(d2p + idx) = out[2];
+      {
+        // rows past ny and lanes past nx write to the trash area (no branch)
+        const bool ok = t < ny && lane_ok;
+        const long idx = (long)t * rs + xc;
+        S *trash = static_cast<S *>(a.trash) + lane * VEC;
+        const long tq = 1024 / sizeof(S);
+        *reinterpret_cast<SP *>(ok ? d0p + idx : trash) = out[0];
+        *reinterpret_cast<SP *>(ok ? d1p + idx : trash + tq) = out[1];
+        *reinterpret_cast<SP *>(ok ? d2p + idx : trash + 2 * tq) = out[2];
       }
     }
 
@@ -356,9 +375,17 @@ __device__ __forceinline__ void strip_body(const StepArgs &a, const int cx0, con
     }
   };
 
-  for (int i = 0; i < NY + 2; i += 2) {
-    body(i, upA);
-    body(i + 1, upB);
+  // Fully unrolled so that every ring slot and up-buffer role is static.
+  constexpr int PF = kPrefetch;
+  Row ring[PF + 1];
+#pragma unroll
+  for (int i = 0; i < PF; ++i) load_row(i, ring[i]);
+#pragma unroll
+  for (int i = 0; i < NY + 2; ++i) {
+    if (i + PF < NY + 2) load_row(i + PF, ring[(i + PF) % (PF + 1)]);
+    // keep the scheduler from sinking those loads down to their use
+    __builtin_amdgcn_sched_barrier(0);
+    body(i, (i & 1) ? upB : upA, ring[i % (PF + 1)]);
   }
 }
 
@@ -372,10 +399,14 @@ __global__ void __launch_bounds__(256) k_step_strip(StepArgs a, StripMap m) {
   const int end = min(m.units, begin + m.per_xcd);
   const int stride = m.persistent ? (int)(gridDim.x >> 3) : m.units;
   for (int u = begin + local; u < end; u += stride) {
-    const int s = u * 4 + wave;  // strips ordered down each column band
-    const int sx = s / m.strips_y;
-    const int sy = s - sx * m.strips_y;
-    if (sx < m.strips_x) strip_body<P, HASWALL, WALL, VEC, NY>(a, sx * 64 * VEC, sy * NY, lane);
+    // strips ordered along each row band (x fastest): the waves of a block and
+    // the blocks of an XCD work on horizontally adjacent strips at the same
+    // time, so the cache lines holding a strip's halo columns are the ones its
+    // neighbours are reading, and the halo rows of the next band follow soon
+    const int s = u * 4 + wave;
+    const int sy = s / m.strips_x;
+    const int sx = s - sy * m.strips_x;
+    if (sy < m.strips_y) strip_body<P, HASWALL, WALL, VEC, NY>(a, sx * 64 * VEC, sy * NY, lane);
   }
 }
 
@@ -398,8 +429,8 @@ __global__ void __launch_bounds__(256) k_reduce_partial(ReduceArgs a) {
   for (long k = (long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x) {
     const int y = (int)(k / a.nx);
     const int x = (int)(k - (long)y * a.nx);
-    const long i = (long)y * a.pitch + x;
-    if (a.flags && a.flags[i] != NODE_FLUID) continue;
+    const long i = (long)y * a.rs + x;
+    if (a.flags && a.flags[(long)y * a.pitch + x] != NODE_FLUID) continue;
     const S r0 = c0[i], r1 = c1[i], r2 = c2[i];
     const double d = (double)T::dec(r0) * a.sc_d;
     const double jx = (double)T::dec(r1) * a.sc_j;
@@ -477,6 +508,7 @@ __global__ void __launch_bounds__(256) k_step_batch(BatchStepArgs b) {
     a.nx = g.nx;
     a.ny = g.ny;
     a.pitch = g.pitch;
+    a.rs = g.rs;
     a.periodic = g.periodic;
     a.fx = g.fx;
     a.fy = g.fy;
@@ -484,8 +516,9 @@ __global__ void __launch_bounds__(256) k_step_batch(BatchStepArgs b) {
     a.sc_j = g.sc_j;
     a.is_d = g.is_d;
     a.is_j = g.is_j;
-    const int sx = item.y / g.strips_y;
-    const int sy = item.y - sx * g.strips_y;
+    a.trash = g.trash;
+    const int sy = item.y / g.strips_x;   // along each row band, as in k_step_strip
+    const int sx = item.y - sy * g.strips_x;
     if (g.wall == WALL_PAPER)
       strip_body<P, true, WALL_PAPER, VEC, NY>(a, sx * 64 * VEC, sy * NY, lane);
     else
@@ -515,8 +548,8 @@ __global__ void __launch_bounds__(256) k_reduce_batch(BatchReduceArgs b) {
     for (long m = threadIdx.x; m < nn; m += blockDim.x) {
       const int y = (int)(m / g.nx);
       const int x = (int)(m - (long)y * g.nx);
-      const long i = (long)y * g.pitch + x;
-      if (g.flags[i] != NODE_FLUID) continue;
+      const long i = (long)y * g.rs + x;
+      if (g.flags[(long)y * g.pitch + x] != NODE_FLUID) continue;
       const S r0 = c0[i], r1 = c1[i], r2 = c2[i];
       const double d = (double)T::dec(r0) * g.sc_d;
       const double jx = (double)T::dec(r1) * g.sc_j;

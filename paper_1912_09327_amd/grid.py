@@ -37,14 +37,14 @@ class Grid:
     """One ``nx`` x ``ny`` lattice.  Arrays are numpy ``[ny, nx]`` (x fastest)."""
 
     def __init__(self, nx, ny, prec="f32", wall="paper", periodic=0, force=(0.0, 0.0),
-                 scale=(0.0, 0.0), snapshot=True, stream=None, torch_memory=True):
+                 scale=(0.0, 0.0), snapshot=True, stream=None, torch_memory=True, planar=False):
         import torch
         self.nx, self.ny = int(nx), int(ny)
         self.prec = _prec(prec)
         self.wall = _wall(wall)
         self.periodic = int(periodic)
         self.force = (float(force[0]), float(force[1]))
-        self.options = C.OPT_SNAPSHOT if snapshot else 0
+        self.options = (C.OPT_SNAPSHOT if snapshot else 0) | (C.OPT_PLANAR if planar else 0)
         self.stream = stream if stream is not None else default_stream()
         nbytes = C.grid_bytes(self.nx, self.ny, self.prec, self.options)
         if nbytes == 0:

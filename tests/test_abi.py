@@ -32,12 +32,13 @@ def test_grid_bytes_is_two_parities_of_three_planes_plus_flags():
     for prec, c in ((C.F64, 8), (C.F32, 4), (C.F16S, 2), (C.BF16S, 2)):
         for nx, ny in ((64, 32), (1000, 1000), (8192, 8192), (37, 5)):
             pitch = (nx + 63) // 64 * 64
-            plane = -(-pitch * ny * c // 256) * 256
             flags = -(-pitch * ny // 256) * 256
-            base = C.grid_bytes(nx, ny, prec, 0)
-            assert base >= 6 * plane + flags
-            assert base - (6 * plane + flags) <= 64 * 1024          # reduction workspace only
-            assert C.grid_bytes(nx, ny, prec, C.OPT_SNAPSHOT) == base + 3 * plane
+            for opt, state in ((0, -(-3 * pitch * ny * c // 256) * 256),                 # [ny][3][pitch]
+                               (C.OPT_PLANAR, 3 * (-(-pitch * ny * c // 256) * 256))):  # [3][ny][pitch]
+                base = C.grid_bytes(nx, ny, prec, opt)
+                assert base >= 2 * state + flags
+                assert base - (2 * state + flags) <= 64 * 1024      # reduction workspace only
+                assert C.grid_bytes(nx, ny, prec, opt | C.OPT_SNAPSHOT) == base + state
     # the paper's 1000 x 1000 float example: 24 bytes per node of moments; rows
     # padded to 1024 values here
     assert 6 * 4 * 1024 * 1000 <= C.grid_bytes(1000, 1000, C.F32, 0) < 6 * 4 * 1024 * 1000 + 1_200_000
