@@ -106,25 +106,11 @@ def timed_run(g, steps, warmup, torch):
     return wall, kern_ms / steps
 
 
-def copy_ceiling(torch, nbytes=2 << 30):
-    """Achievable HBM bandwidth of a plain device copy (read + write) on this GPU."""
-    x = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
-    y = torch.empty_like(x)
-    x.fill_(1.0)
-    for _ in range(3):
-        y.copy_(x)
-    torch.cuda.synchronize()
-    a = torch.cuda.Event(enable_timing=True)
-    b = torch.cuda.Event(enable_timing=True)
-    reps = 10
-    a.record()
-    for _ in range(reps):
-        y.copy_(x)
-    b.record()
-    torch.cuda.synchronize()
-    ms = a.elapsed_time(b) / reps
-    del x, y
-    return 2 * nbytes / (ms * 1e-3) / 1e9
+def copy_ceiling(nbytes=2 << 30):
+    """Achievable bandwidth of a plain streaming copy on this GPU (the library's probe:
+    1 GiB read and 1 GiB written per launch, best launch shape)."""
+    from paper_1912_09327_amd import _capi as C
+    return C.probe_bandwidth(C.PROBE_COPY, nbytes, nontemporal=False, reps=3)
 
 
 def cpu_baseline(state, budget_s):
@@ -213,7 +199,7 @@ def run_periodic(args, torch):
                      "bytes_per_lup": 2 * 3 * c, "kernel_ms": round(head["kernel_ms"], 5)},
     }
     try:
-        cc = copy_ceiling(torch)
+        cc = copy_ceiling()
         line["roofline"]["copy_ceiling_GBps"] = round(cc, 1)
         line["roofline"]["frac_of_copy"] = round(head["achieved"] / cc, 4)
     except Exception as e:  # pragma: no cover - measurement aid only

@@ -29,14 +29,42 @@ FLAGS = [
 ]
 
 
+def _resources(text):
+    """Per-kernel (scratch bytes, SGPR spills, VGPR spills) from the compiler's
+    kernel-resource-usage remarks."""
+    res, name = {}, None
+    for ln in text.splitlines():
+        if "Function Name:" in ln:
+            name = ln.split("Function Name:")[1].split("[")[0].strip()
+            res[name] = [0, 0, 0]
+        elif name and "ScratchSize [bytes/lane]:" in ln:
+            res[name][0] = int(ln.split("ScratchSize [bytes/lane]:")[1].split("[")[0])
+        elif name and "SGPRs Spill:" in ln:
+            res[name][1] = int(ln.split("SGPRs Spill:")[1].split("[")[0])
+        elif name and "VGPRs Spill:" in ln:
+            res[name][2] = int(ln.split("VGPRs Spill:")[1].split("[")[0])
+    return res
+
+
 def _compile(src, out, verbose):
     cmd = [HIPCC] + FLAGS + ["-c", os.path.join(CSRC, src), "-o", out]
+    if src == "lbt1_kernels.hip":
+        cmd.append("-Rpass-analysis=kernel-resource-usage")
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
     lines = [ln for ln in (r.stdout + r.stderr).splitlines() if "packed-fp32-ops" not in ln]
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n" + "\n".join(lines))
+    if src == "lbt1_kernels.hip":
+        # No step kernel may spill registers or use scratch memory: the strip
+        # kernels are sized to stay in registers, and a spilling variant is a
+        # design error (it is not built).
+        bad = {k: v for k, v in _resources(r.stdout + r.stderr).items() if any(v)}
+        if bad:
+            raise RuntimeError("kernels spill or use scratch (scratch B/lane, SGPR, VGPR spills): "
+                               + "; ".join(f"{k}: {v}" for k, v in sorted(bad.items())))
+        lines = [ln for ln in lines if "kernel-resource-usage" not in ln]
     return "\n".join(lines)
 
 

@@ -1,6 +1,6 @@
 // Batched stepping of many resident grids (lbt1_batch_* of include/lbt1.h).
 //
-// Every resident grid is cut into strips (64*vec columns by 14 rows); the
+// Every resident grid is cut into strips (62*vec columns by 14 rows); the
 // strips of all grids with the same columns-per-lane class form one work
 // list, and one launch per class and time step covers the whole list, so a
 // step of hundreds of small, uneven grids costs a handful of launches.  A
@@ -68,7 +68,7 @@ namespace lbt1 {
 static const int kVecOfClass[4] = {1, 2, 4, 8};
 
 static int vec_class_for(int prec, int nx) {
-  const int maxc = prec == LBT1_F64 ? 1 : prec == LBT1_F32 ? 2 : 3;
+  const int maxc = prec == LBT1_F64 ? 1 : 2;  // the batched kernels go up to 4 columns per lane
   for (int c = maxc; c >= 0; --c) {
     const int v = kVecOfClass[c];
     if (nx % v == 0 && 64 * v <= std::max(64, nx)) return c;
@@ -82,7 +82,7 @@ static void rebuild_items(lbt1_batch *b) {
     const Slot &sl = b->slots[s];
     if (sl.state == LBT1_SLOT_FREE) continue;
     const int v = kVecOfClass[sl.vclass];
-    const int sx = (sl.g->nx + 64 * v - 1) / (64 * v);
+    const int sx = (sl.g->nx / v + 61) / 62;  // strips of 62 chunks of v columns
     const int sy = (sl.g->ny + 13) / 14;
     for (int k = 0; k < sx * sy; ++k) b->items[sl.vclass].push_back(make_int2(s, k));
   }
@@ -272,7 +272,7 @@ lbt1_status lbt1_batch_admit(lbt1_batch *b, lbt1_grid *g, int64_t step_budget, d
   d.wall = g->wall;
   d.parity0 = g->parity;
   d.steps_left = 0;
-  d.strips_x = (g->nx + 64 * kVecOfClass[sl.vclass] - 1) / (64 * kVecOfClass[sl.vclass]);
+  d.strips_x = (g->nx / kVecOfClass[sl.vclass] + 61) / 62;
   d.fx = g->F[0];
   d.fy = g->F[1];
   d.sc_d = g->sc[0];

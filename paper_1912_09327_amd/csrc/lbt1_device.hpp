@@ -142,11 +142,13 @@ struct StepArgs {
                        // rows outside the grid, so that stores need no branch
 };
 
-// Source coordinate along one axis: wrapped when periodic, -1 when outside.
+// Source coordinate along one axis: wrapped when periodic (any distance, so
+// strips taller than a small periodic grid stay in bounds), -1 when outside.
 __device__ __forceinline__ int wrap_axis(int c, int n, bool periodic) {
-  if (c < 0) return periodic ? c + n : -1;
-  if (c >= n) return periodic ? c - n : -1;
-  return c;
+  if (c >= 0 && c < n) return c;
+  if (!periodic) return -1;
+  c %= n;
+  return c < 0 ? c + n : c;
 }
 
 template <int P>

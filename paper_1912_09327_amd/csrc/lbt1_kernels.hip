@@ -26,14 +26,18 @@ __global__ void __launch_bounds__(64) k_reduce_final(const double *partials, int
    "k_step_strip<" #P "," #HW "," #W "," #V "," #R ">"}
 #define STRIP_WALLS(P, V, R) STRIP(P, false, 0, V, R), STRIP(P, true, 0, V, R), STRIP(P, true, 1, V, R)
 #define STRIP_ROWS(P, V) STRIP_WALLS(P, V, 14), STRIP_WALLS(P, V, 30)
+// 8 columns per lane only without walls: the wall-aware variants at that width
+// need more registers than a wavefront has and spill (the build refuses any
+// kernel that spills or uses scratch memory)
+#define STRIP_ROWS_NOWALL(P, V) STRIP(P, false, 0, V, 14), STRIP(P, false, 0, V, 30)
 #define GATHER_ALL(P) GATHER(P, false, 0), GATHER(P, true, 0), GATHER(P, true, 1)
 
 static const StepKernel kTable[] = {
     GATHER_ALL(P_F64),     GATHER_ALL(P_F32),     GATHER_ALL(P_F16S),    GATHER_ALL(P_BF16S),
     STRIP_ROWS(P_F64, 1),  STRIP_ROWS(P_F64, 2),  STRIP_ROWS(P_F32, 1),  STRIP_ROWS(P_F32, 2),
     STRIP_ROWS(P_F32, 4),  STRIP_ROWS(P_F16S, 1), STRIP_ROWS(P_F16S, 2), STRIP_ROWS(P_F16S, 4),
-    STRIP_ROWS(P_F16S, 8), STRIP_ROWS(P_BF16S, 1), STRIP_ROWS(P_BF16S, 2), STRIP_ROWS(P_BF16S, 4),
-    STRIP_ROWS(P_BF16S, 8),
+    STRIP_ROWS_NOWALL(P_F16S, 8), STRIP_ROWS(P_BF16S, 1), STRIP_ROWS(P_BF16S, 2), STRIP_ROWS(P_BF16S, 4),
+    STRIP_ROWS_NOWALL(P_BF16S, 8),
 };
 
 const StepKernel *step_kernels(int *count) {
@@ -53,13 +57,10 @@ const void *reduce_partial_kernel(int prec) {
 
 const void *reduce_final_kernel() { return (const void *)&k_reduce_final; }
 
-// Batched kernels: [precision][vec class 0..3 = vec 1, 2, 4, 8]; strips of 14 rows.
+// Batched kernels (always wall-aware): [precision][vec class 0..2 = vec 1, 2, 4];
+// strips of 14 rows.
 #define BATCH_ROW(P) \
-  {(const void *)&k_step_batch<P, 1, 14>, (const void *)&k_step_batch<P, 2, 14>, (const void *)&k_step_batch<P, 4, 14>, B8_##P}
-#define B8_P_F64 nullptr
-#define B8_P_F32 nullptr
-#define B8_P_F16S (const void *)&k_step_batch<P_F16S, 8, 14>
-#define B8_P_BF16S (const void *)&k_step_batch<P_BF16S, 8, 14>
+  {(const void *)&k_step_batch<P, 1, 14>, (const void *)&k_step_batch<P, 2, 14>, (const void *)&k_step_batch<P, 4, 14>, nullptr}
 
 const void *batch_step_kernel(int prec, int vec_class) {
   static const void *table[4][4] = {

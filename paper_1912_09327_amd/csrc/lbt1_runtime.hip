@@ -293,7 +293,7 @@ lbt1_status bind_config(lbt1_grid *g, const lbt1_kernel_config &want, int cus) {
     g->grid = dim3((g->nx + 63) / 64, (g->ny + 3) / 4, 1);
   } else {
     StripMap &m = g->map;
-    m.strips_x = (g->nx + 64 * c.vec - 1) / (64 * c.vec);
+    m.strips_x = (g->nx / c.vec + 61) / 62;  // 62 chunks of vec columns per strip
     m.strips_y = (g->ny + c.rows - 1) / c.rows;
     const int strips = m.strips_x * m.strips_y;
     m.units = (strips + 3) / 4;

@@ -6,13 +6,12 @@
 //
 //  * gather: one thread per node reads its nine upwind neighbours.  Simple,
 //    any size; the nine reads per node are served by the caches.
-//  * strip: one wavefront walks a strip of NY rows; each lane owns VEC
-//    adjacent columns.  Every source node's moments are read once per strip
-//    and its nine emissions computed once; the emissions that cross to the
-//    neighbouring column go through a one-lane shuffle, and the two columns
-//    just outside the strip are computed once per strip by a pre-pass whose
-//    lanes each take one (row, side) pair.  A strip reads its NY rows plus one
-//    halo row above and below.
+//  * strip: one wavefront walks a strip of NY rows and 62 chunks of VEC
+//    columns; each lane owns one chunk.  Every source node's moments are read
+//    once per strip and its nine emissions computed once; the emissions that
+//    cross to the neighbouring chunk go through a one-lane shuffle.  A strip
+//    reads its NY rows plus one halo row above and below, and one halo chunk
+//    on each side.
 #pragma once
 #include <type_traits>
 
@@ -26,16 +25,6 @@ struct alignas(sizeof(S) * VEC) Pack {
   S v[VEC];
 };
 
-__device__ __forceinline__ float lane_read(float v, int l) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
-}
-__device__ __forceinline__ double lane_read(double v, int l) {
-  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
-  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
-  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
-  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
-}
-__device__ __forceinline__ int lane_read(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
 
 // ================================================================ gather kernel
 template <int P, bool HASWALL, int WALL>
@@ -109,8 +98,15 @@ struct ArrS {  // the same arrivals already reduced (no walls): row sum and x di
 // Rows whose loads are issued ahead of the row being computed.
 constexpr int kPrefetch = 2;
 
+// A strip is 62 * VEC output columns by NY output rows.  Lane l of the
+// wavefront owns the VEC-column chunk (chunk0 - 1 + l): lanes 1..62 are the
+// strip's own chunks, lane 0 and lane 63 load the neighbouring strips' edge
+// chunks, so every emission that crosses a chunk boundary comes from the lane
+// next door through one shuffle and no separate halo pass is needed.  The halo
+// chunks are aligned vector loads of cache lines the neighbouring strips read
+// at the same time.
 template <int P, bool HASWALL, int WALL, int VEC, int NY>
-__device__ __forceinline__ void strip_body(const StepArgs &a, const int cx0, const int y0,
+__device__ __forceinline__ void strip_body(const StepArgs &a, const int chunk0, const int y0,
                                            const int lane) {
   using T = Traits<P>;
   using C = typename T::C;
@@ -119,7 +115,7 @@ __device__ __forceinline__ void strip_body(const StepArgs &a, const int cx0, con
   using FP = Pack<uint8_t, VEC>;
   static_assert(NY + 2 <= 32, "strip height");
 
-  const int nx = a.nx, ny = a.ny;
+  const int ny = a.ny;
   const long pitch = a.pitch, rs = a.rs;
   const bool px = a.periodic & 1u, py = a.periodic & 2u;
   const C Fx = C(a.fx), Fy = C(a.fy);
@@ -130,41 +126,19 @@ __device__ __forceinline__ void strip_body(const StepArgs &a, const int cx0, con
   S *__restrict__ d0p = static_cast<S *>(a.dst[0]);
   S *__restrict__ d1p = static_cast<S *>(a.dst[1]);
   S *__restrict__ d2p = static_cast<S *>(a.dst[2]);
-  const int xc = cx0 + lane * VEC;
-  const bool lane_ok = xc < nx;
-  const int last_lane = min(63, (nx - 1 - cx0) / VEC);
-
-  // ---- pre-pass: emissions of the two columns just outside the strip.
-  // Lane i < 32 takes the left column at row y0-1+i (it needs the emissions
-  // heading +x: q = 1, 5, 8); lane 32+i the right one (q = 3, 6, 7).
-  C h0 = C(0), h1 = C(0), h2 = C(0);
-  int hs = 1;
-  {
-    const int side = lane >> 5, i = lane & 31;
-    if (i < NY + 2) {
-      const int r = wrap_axis(y0 - 1 + i, ny, py);
-      int c = side == 0 ? cx0 - 1 : cx0 + 64 * VEC;
-      if (side == 1 && c >= nx) c = nx;
-      c = wrap_axis(c, nx, px);
-      if (r >= 0 && c >= 0) {
-        const long idx = (long)r * rs + c;
-        if (!HASWALL || a.flags[(long)r * pitch + c] != NODE_SOLID) {
-          C d = T::dec(s0[idx]), jx = T::dec(s1[idx]), jy = T::dec(s2[idx]);
-          if (T::kScaled) {
-            d *= sd;
-            jx *= sj;
-            jy *= sj;
-          }
-          C f[9];
-          emit<C>(d, jx, jy, Fx, Fy, f);
-          h0 = side == 0 ? f[1] : f[3];
-          h1 = side == 0 ? f[5] : f[6];
-          h2 = side == 0 ? f[8] : f[7];
-          hs = 0;
-        }
-      }
-    }
+  const int nch = a.nx / VEC;  // VEC divides nx
+  const int ch = chunk0 - 1 + lane;
+  // source chunk: wrapped when x is periodic; outside a non-periodic x it is a wall
+  bool col_ok = true;
+  int chw = ch;
+  if (ch < 0 || ch >= nch) {
+    if (px)
+      chw = ((ch % nch) + nch) % nch;
+    else
+      col_ok = false;
   }
+  const int xc = col_ok ? chw * VEC : 0;
+  const bool lane_out = lane >= 1 && lane <= 62 && ch < nch;  // chunks this strip writes
 
   using Arr = typename std::conditional<HASWALL, ArrW<C, VEC>, ArrS<C, VEC>>::type;
   Arr upA, upB, lev;
@@ -182,15 +156,15 @@ __device__ __forceinline__ void strip_body(const StepArgs &a, const int cx0, con
     SP raw[3];
     FP fl;
   };
-  // The loads are unconditional (lanes past the grid's edge and rows outside a
-  // non-periodic axis read row 0 / column 0 instead and are then ignored or
-  // flagged as walls): with no branch around them the compiler keeps exact
-  // track of the loads in flight, which is what lets the prefetch overlap.
+  // The loads are unconditional (chunks and rows outside a non-periodic axis
+  // read column 0 / row 0 instead and are flagged as walls): with no branch
+  // around them the compiler keeps exact track of the loads in flight, which
+  // is what lets the prefetch overlap.
   auto load_row = [&](const int i, Row &dst) __attribute__((always_inline)) {
     const int rr = wrap_axis(y0 - 1 + i, ny, py);
     const bool row_ok = rr >= 0;
     const long row = row_ok ? rr : 0;
-    const long col = lane_ok ? xc : 0;
+    const long col = xc;
     const long idx = row * rs + col;
     dst.raw[0] = *reinterpret_cast<const SP *>(s0 + idx);
     dst.raw[1] = *reinterpret_cast<const SP *>(s1 + idx);
@@ -198,7 +172,7 @@ __device__ __forceinline__ void strip_body(const StepArgs &a, const int cx0, con
     if (HASWALL) {
       const FP f = *reinterpret_cast<const FP *>(a.flags + row * pitch + col);
 #pragma unroll
-      for (int v = 0; v < VEC; ++v) dst.fl.v[v] = row_ok ? f.v[v] : (uint8_t)NODE_SOLID;
+      for (int v = 0; v < VEC; ++v) dst.fl.v[v] = (row_ok && col_ok) ? f.v[v] : (uint8_t)NODE_SOLID;
     }
   };
 
@@ -227,36 +201,18 @@ __device__ __forceinline__ void strip_body(const StepArgs &a, const int cx0, con
     }
     (void)dd;
     (void)fbits;
-    // neighbour-lane emissions: heading +x from the lane on the left, -x from the right
-    C L1 = __shfl_up(f[VEC - 1][1], 1);
-    C L5 = __shfl_up(f[VEC - 1][5], 1);
-    C L8 = __shfl_up(f[VEC - 1][8], 1);
-    C R3 = __shfl_down(f[0][3], 1);
-    C R6 = __shfl_down(f[0][6], 1);
-    C R7 = __shfl_down(f[0][7], 1);
+    // neighbour-lane emissions: heading +x from the lane on the left, -x from
+    // the right (lanes 0 and 63 receive nothing useful; they write nothing)
+    const C L1 = __shfl_up(f[VEC - 1][1], 1);
+    const C L5 = __shfl_up(f[VEC - 1][5], 1);
+    const C L8 = __shfl_up(f[VEC - 1][8], 1);
+    const C R3 = __shfl_down(f[0][3], 1);
+    const C R6 = __shfl_down(f[0][6], 1);
+    const C R7 = __shfl_down(f[0][7], 1);
     int Ls = 0, Rs = 0;
     if (HASWALL) {
       Ls = __shfl_up((int)((sbits >> (VEC - 1)) & 1u), 1);
       Rs = __shfl_down((int)(sbits & 1u), 1);
-    }
-    {
-      const C e0 = lane_read(h0, i), e1 = lane_read(h1, i), e2 = lane_read(h2, i);
-      const C g0 = lane_read(h0, 32 + i), g1 = lane_read(h1, 32 + i), g2 = lane_read(h2, 32 + i);
-      if (lane == 0) {
-        L1 = e0;
-        L5 = e1;
-        L8 = e2;
-      }
-      if (lane == last_lane) {
-        R3 = g0;
-        R6 = g1;
-        R7 = g2;
-      }
-      if (HASWALL) {
-        const int es = lane_read(hs, i), gs = lane_read(hs, 32 + i);
-        if (lane == 0) Ls = es;
-        if (lane == last_lane) Rs = gs;
-      }
     }
     // wall bits of the left / own / right source of column v
     auto bit_l = [&](int v) -> uint32_t { return v > 0 ? (sbits >> (v - 1)) & 1u : (uint32_t)Ls; };
@@ -320,7 +276,7 @@ __device__ __forceinline__ void strip_body(const StepArgs &a, const int cx0, con
       }
       {
         // rows past ny and lanes past nx write to the trash area (no branch)
-        const bool ok = t < ny && lane_ok;
+        const bool ok = t < ny && lane_out;
         const long idx = (long)t * rs + xc;
         S *trash = static_cast<S *>(a.trash) + lane * VEC;
         const long tq = 1024 / sizeof(S);
@@ -406,7 +362,7 @@ __global__ void __launch_bounds__(256) k_step_strip(StepArgs a, StripMap m) {
     const int s = u * 4 + wave;
     const int sy = s / m.strips_x;
     const int sx = s - sy * m.strips_x;
-    if (sy < m.strips_y) strip_body<P, HASWALL, WALL, VEC, NY>(a, sx * 64 * VEC, sy * NY, lane);
+    if (sy < m.strips_y) strip_body<P, HASWALL, WALL, VEC, NY>(a, sx * 62, sy * NY, lane);
   }
 }
 
@@ -520,9 +476,9 @@ __global__ void __launch_bounds__(256) k_step_batch(BatchStepArgs b) {
     const int sy = item.y / g.strips_x;   // along each row band, as in k_step_strip
     const int sx = item.y - sy * g.strips_x;
     if (g.wall == WALL_PAPER)
-      strip_body<P, true, WALL_PAPER, VEC, NY>(a, sx * 64 * VEC, sy * NY, lane);
+      strip_body<P, true, WALL_PAPER, VEC, NY>(a, sx * 62, sy * NY, lane);
     else
-      strip_body<P, true, WALL_HALFWAY, VEC, NY>(a, sx * 64 * VEC, sy * NY, lane);
+      strip_body<P, true, WALL_HALFWAY, VEC, NY>(a, sx * 62, sy * NY, lane);
   }
 }
 

