@@ -169,13 +169,15 @@ enum {
   LBT1_KERNEL_GATHER = 1, /* one thread per node, nine neighbour reads */
   LBT1_KERNEL_STRIP = 2   /* a wavefront walks a strip of rows; each lane owns `vec`
                              adjacent columns, neighbour columns come from adjacent
-                             lanes; every moment is read from memory once per strip */
+                             lanes; every moment is read from memory once per strip
+                             (plus one halo row above and below and one halo chunk on
+                             each side) */
 };
 
 typedef struct {
   int32_t kernel; /* LBT1_KERNEL_* */
   int32_t vec;    /* STRIP: columns per lane, 1, 2, 4 or 8 (must divide nx) */
-  int32_t rows;   /* STRIP: rows per strip, 6, 14 or 30 */
+  int32_t rows;   /* STRIP: rows per strip, 6 or 14 */
   int32_t waves;  /* STRIP: resident wavefronts per CU the launch aims at (1..32);
                      0 = one wavefront per strip, no grid-stride loop */
 } lbt1_kernel_config;

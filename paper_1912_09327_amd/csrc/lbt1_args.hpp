@@ -47,13 +47,21 @@ struct BatchStepArgs {
   int step;           // step index inside the burst
 };
 
-// Per-grid diagnostics after a burst: one block per active grid, the six
-// slots of k_reduce_partial, snapshot refreshed.  out[slot * 6 + q].
+// Per-grid diagnostics after a burst (the six slots of k_reduce_partial,
+// snapshot refreshed): every resident grid is cut into chunks of
+// kBatchReduceChunk nodes, one block reduces one chunk into partials[item],
+// then the partials of each active grid are combined in item order into
+// out[slot * 6 + q].
+constexpr int kBatchReduceChunk = 16384;
 struct BatchReduceArgs {
   const BatchGrid *grids;
-  void *const *snaps;  // 3 per slot
-  const int *active;   // slots to reduce
+  void *const *snaps;   // 3 per slot
+  const int2 *items;    // (slot, chunk) of every resident grid
+  const int *nitems;
+  double *partials;     // 6 per item
+  const int *active;    // slots reduced this burst
   const int *nactive;
+  const int2 *ranges;   // per slot: first item, number of items
   double *out;
 };
 

@@ -1,14 +1,18 @@
 // Batched stepping of many resident grids (lbt1_batch_* of include/lbt1.h).
 //
-// Every resident grid is cut into strips (62*vec columns by 14 rows); the
+// Every resident grid is cut into strips (62*vec columns by 14 or 6 rows); the
 // strips of all grids with the same columns-per-lane class form one work
 // list, and one launch per class and time step covers the whole list, so a
 // step of hundreds of small, uneven grids costs a handful of launches.  A
-// burst of K steps plus the per-grid residual check is one HIP graph; the
-// grid descriptors and work lists live in device memory, so admitting or
-// finishing grids changes data, not the graph (it is rebuilt only when the
-// burst length or the set of non-empty classes changes, or a list outgrows
-// its allocation).
+// class whose list is too short to give every CU several wavefronts uses
+// 6-row strips (a strip walks its rows one after another, so short strips cut
+// the latency of a step).  A burst of K steps plus the per-grid residual check
+// is one HIP graph with one chain of step launches per class (the classes
+// touch disjoint grids, so their chains run side by side); the grid
+// descriptors and work lists live in device memory, so admitting or finishing
+// grids changes data, not the graph (it is rebuilt only when the burst length,
+// the set of non-empty classes or a class's strip height changes, or a list
+// outgrows its allocation).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -46,20 +50,29 @@ struct lbt1_batch {
   lbt1::BatchGrid *d_grids = nullptr;
   void **d_snaps = nullptr;
   int *d_active = nullptr;
-  int *d_counts = nullptr;  // [4] item counts, [4] active count
+  int *d_counts = nullptr;  // [0..3] item counts per class, [4] active slots, [5] reduction items
   double *d_red = nullptr;
   int2 *d_items[4] = {nullptr, nullptr, nullptr, nullptr};
   size_t item_cap[4] = {0, 0, 0, 0};
+  int2 *d_ritems = nullptr;  // reduction items (slot, chunk)
+  double *d_partials = nullptr;
+  size_t ritem_cap = 0;
+  int2 *d_ranges = nullptr;  // per slot: first reduction item, count
   // pinned host mirrors
   lbt1::BatchGrid *h_grids = nullptr;
   void **h_snaps = nullptr;
   int *h_active = nullptr;
   int *h_counts = nullptr;
   double *h_red = nullptr;
+  int2 *h_ranges = nullptr;
   std::vector<int2> items[4];
+  std::vector<int2> ritems;
+  int rows[4] = {14, 14, 14, 14};  // strip height per class
+  int blocks[4] = {0, 0, 0, 0};    // launch size per class
   bool items_dirty = true;
   hipGraphExec_t graph = nullptr;
   int graph_K = 0, graph_mask = -1;
+  long graph_shape = -1;
   bool graph_valid = false;
 };
 
@@ -76,17 +89,55 @@ static int vec_class_for(int prec, int nx) {
   return 0;
 }
 
+// Launch size of a class: as many 256-thread blocks as the kernel's register
+// use lets every CU hold at once, but no more than the class has work items
+// for (each block takes four strips per pass).
+static int class_blocks(const lbt1_batch *b, int c) {
+  const void *fn = batch_step_kernel(b->prec, c, b->rows[c]);
+  int per_cu = 2;
+  if (fn) (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, 0);
+  per_cu = std::max(1, per_cu);
+  const long need = ((long)b->items[c].size() + 3) / 4;
+  return (int)std::max<long>(1, std::min<long>((long)per_cu * b->cus, need));
+}
+
+static long graph_shape(const lbt1_batch *b) {
+  long key = 0;
+  for (int c = 0; c < 4; ++c) key = key * 1000003L + b->rows[c] * 100003L + b->blocks[c];
+  return key;
+}
+
 static void rebuild_items(lbt1_batch *b) {
-  for (int c = 0; c < 4; ++c) b->items[c].clear();
+  long tall[4] = {0, 0, 0, 0};
   for (int s = 0; s < b->max_slots; ++s) {
     const Slot &sl = b->slots[s];
     if (sl.state == LBT1_SLOT_FREE) continue;
     const int v = kVecOfClass[sl.vclass];
-    const int sx = (sl.g->nx / v + 61) / 62;  // strips of 62 chunks of v columns
-    const int sy = (sl.g->ny + 13) / 14;
-    for (int k = 0; k < sx * sy; ++k) b->items[sl.vclass].push_back(make_int2(s, k));
+    tall[sl.vclass] += (long)((sl.g->nx / v + 61) / 62) * ((sl.g->ny + 13) / 14);
   }
+  for (int c = 0; c < 4; ++c) {
+    b->items[c].clear();
+    b->rows[c] = tall[c] < 8L * b->cus ? 6 : 14;
+  }
+  // (block counts are set below, once the lists are built)
+  b->ritems.clear();
+  for (int s = 0; s < b->max_slots; ++s) {
+    const Slot &sl = b->slots[s];
+    b->h_ranges[s] = make_int2(0, 0);
+    if (sl.state == LBT1_SLOT_FREE) continue;
+    const int v = kVecOfClass[sl.vclass];
+    const int rows = b->rows[sl.vclass];
+    const int sx = (sl.g->nx / v + 61) / 62;  // strips of 62 chunks of v columns
+    const int sy = (sl.g->ny + rows - 1) / rows;
+    for (int k = 0; k < sx * sy; ++k) b->items[sl.vclass].push_back(make_int2(s, k));
+    const long nodes = (long)sl.g->nx * sl.g->ny;
+    const int chunks = (int)((nodes + kBatchReduceChunk - 1) / kBatchReduceChunk);
+    b->h_ranges[s] = make_int2((int)b->ritems.size(), chunks);
+    for (int k = 0; k < chunks; ++k) b->ritems.push_back(make_int2(s, k));
+  }
+  for (int c = 0; c < 4; ++c) b->blocks[c] = b->items[c].empty() ? 0 : class_blocks(b, c);
 }
+
 
 static lbt1_status upload_items(lbt1_batch *b) {
   hipError_t e;
@@ -107,6 +158,28 @@ static lbt1_status upload_items(lbt1_batch *b) {
       return hip_fail(e, "items H2D");
     b->h_counts[c] = (int)n;
   }
+  const size_t nr = b->ritems.size();
+  if (nr > b->ritem_cap) {
+    size_t cap = std::max<size_t>(1024, b->ritem_cap);
+    while (cap < nr) cap *= 2;
+    if (b->d_ritems) (void)hipFree(b->d_ritems);
+    if (b->d_partials) (void)hipFree(b->d_partials);
+    b->d_ritems = nullptr;
+    b->d_partials = nullptr;
+    b->ritem_cap = 0;
+    if ((e = hipMalloc(&b->d_ritems, cap * sizeof(int2))) != hipSuccess ||
+        (e = hipMalloc(&b->d_partials, cap * 6 * sizeof(double))) != hipSuccess)
+      return hip_fail(e, "hipMalloc reduction items");
+    b->ritem_cap = cap;
+    b->graph_valid = false;
+  }
+  if (nr && (e = hipMemcpyAsync(b->d_ritems, b->ritems.data(), nr * sizeof(int2), hipMemcpyHostToDevice, b->stream)) !=
+                hipSuccess)
+    return hip_fail(e, "reduction items H2D");
+  if ((e = hipMemcpyAsync(b->d_ranges, b->h_ranges, (size_t)b->max_slots * sizeof(int2), hipMemcpyHostToDevice,
+                          b->stream)) != hipSuccess)
+    return hip_fail(e, "ranges H2D");
+  b->h_counts[5] = (int)nr;
   b->items_dirty = false;
   return LBT1_OK;
 }
@@ -115,26 +188,27 @@ static lbt1_status build_graph(lbt1_batch *b, int K, int mask) {
   hipError_t e;
   hipGraph_t graph = nullptr;
   if ((e = hipGraphCreate(&graph, 0)) != hipSuccess) return hip_fail(e, "hipGraphCreate");
-  hipGraphNode_t prev = nullptr;
-  const int blocks = std::max(8, b->cus * 2);  // 8 wavefronts per CU
   std::vector<BatchStepArgs> argv;
   argv.reserve((size_t)K * 4);
-  auto add = [&](const void *fn, dim3 grid, dim3 block, void **args) -> lbt1_status {
+  auto add = [&](const void *fn, dim3 grid, dim3 block, void **args, const hipGraphNode_t *deps, int ndeps,
+                 hipGraphNode_t *out) -> lbt1_status {
     hipKernelNodeParams kp{};
     kp.func = const_cast<void *>(fn);
     kp.gridDim = grid;
     kp.blockDim = block;
     kp.kernelParams = args;
-    hipGraphNode_t node;
-    hipError_t err = hipGraphAddKernelNode(&node, graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
+    hipError_t err = hipGraphAddKernelNode(out, graph, ndeps ? deps : nullptr, ndeps, &kp);
     if (err != hipSuccess) return hip_fail(err, "hipGraphAddKernelNode");
-    prev = node;
     return LBT1_OK;
   };
+  // one chain per class: step s of a class waits for step s - 1 of the same class
   lbt1_status st = LBT1_OK;
-  for (int s = 0; s < K && !st; ++s) {
-    for (int c = 0; c < 4 && !st; ++c) {
-      if (!(mask & (1 << c))) continue;
+  hipGraphNode_t last[4];
+  int nlast = 0;
+  for (int c = 0; c < 4 && !st; ++c) {
+    if (!(mask & (1 << c))) continue;
+    hipGraphNode_t prev = nullptr;
+    for (int s = 0; s < K && !st; ++s) {
       BatchStepArgs a;
       a.grids = b->d_grids;
       a.items = b->d_items[c];
@@ -142,18 +216,32 @@ static lbt1_status build_graph(lbt1_batch *b, int K, int mask) {
       a.step = s;
       argv.push_back(a);
       void *args[] = {&argv.back()};
-      st = add(batch_step_kernel(b->prec, c), dim3(blocks), dim3(256), args);
+      hipGraphNode_t node;
+      st = add(batch_step_kernel(b->prec, c, b->rows[c]), dim3(b->blocks[c]), dim3(256), args, &prev,
+               prev ? 1 : 0, &node);
+      prev = node;
     }
+    last[nlast++] = prev;
   }
   BatchReduceArgs ra;
   ra.grids = b->d_grids;
   ra.snaps = b->d_snaps;
+  ra.items = b->d_ritems;
+  ra.nitems = b->d_counts + 5;
+  ra.partials = b->d_partials;
   ra.active = b->d_active;
   ra.nactive = b->d_counts + 4;
+  ra.ranges = b->d_ranges;
   ra.out = b->d_red;
+  hipGraphNode_t partial;
   if (!st) {
     void *args[] = {&ra};
-    st = add(batch_reduce_kernel(b->prec), dim3(std::max(8, b->cus * 2)), dim3(256), args);
+    st = add(batch_reduce_kernel(b->prec), dim3(std::max(8, b->cus * 4)), dim3(256), args, last, nlast, &partial);
+  }
+  if (!st) {
+    void *args[] = {&ra};
+    hipGraphNode_t node;
+    st = add(batch_reduce_final_kernel(), dim3(std::max(8, b->cus)), dim3(64), args, &partial, 1, &node);
   }
   if (st) {
     (void)hipGraphDestroy(graph);
@@ -166,6 +254,7 @@ static lbt1_status build_graph(lbt1_batch *b, int K, int mask) {
   if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
   b->graph_K = K;
   b->graph_mask = mask;
+  b->graph_shape = graph_shape(b);
   b->graph_valid = true;
   return LBT1_OK;
 }
@@ -205,6 +294,8 @@ lbt1_status lbt1_batch_create(size_t hbm_budget_bytes, int32_t max_slots, void *
             hipMalloc(&b->d_active, ns * sizeof(int)) == hipSuccess &&
             hipMalloc(&b->d_counts, 8 * sizeof(int)) == hipSuccess &&
             hipMalloc(&b->d_red, ns * 6 * sizeof(double)) == hipSuccess &&
+            hipMalloc(&b->d_ranges, ns * sizeof(int2)) == hipSuccess &&
+            hipHostMalloc((void **)&b->h_ranges, ns * sizeof(int2), hipHostMallocDefault) == hipSuccess &&
             hipHostMalloc((void **)&b->h_grids, ns * sizeof(BatchGrid), hipHostMallocDefault) == hipSuccess &&
             hipHostMalloc((void **)&b->h_snaps, ns * 3 * sizeof(void *), hipHostMallocDefault) == hipSuccess &&
             hipHostMalloc((void **)&b->h_active, ns * sizeof(int), hipHostMallocDefault) == hipSuccess &&
@@ -321,7 +412,7 @@ lbt1_status lbt1_batch_run(lbt1_batch *b, int32_t burst_steps) {
       (e = hipMemcpyAsync(b->d_active, b->h_active, (size_t)nact * sizeof(int), hipMemcpyHostToDevice, b->stream)) != hipSuccess ||
       (e = hipMemcpyAsync(b->d_counts, b->h_counts, 8 * sizeof(int), hipMemcpyHostToDevice, b->stream)) != hipSuccess)
     return hip_fail(e, "descriptor H2D");
-  if (!b->graph_valid || b->graph_K != burst_steps || b->graph_mask != mask) {
+  if (!b->graph_valid || b->graph_K != burst_steps || b->graph_mask != mask || b->graph_shape != graph_shape(b)) {
     lbt1_status st = build_graph(b, burst_steps, mask);
     if (st) return st;
   }
@@ -410,6 +501,10 @@ lbt1_status lbt1_batch_destroy(lbt1_batch *b) {
   if (b->d_active) (void)hipFree(b->d_active);
   if (b->d_counts) (void)hipFree(b->d_counts);
   if (b->d_red) (void)hipFree(b->d_red);
+  if (b->d_ranges) (void)hipFree(b->d_ranges);
+  if (b->d_ritems) (void)hipFree(b->d_ritems);
+  if (b->d_partials) (void)hipFree(b->d_partials);
+  if (b->h_ranges) (void)hipHostFree(b->h_ranges);
   if (b->h_grids) (void)hipHostFree(b->h_grids);
   if (b->h_snaps) (void)hipHostFree(b->h_snaps);
   if (b->h_active) (void)hipHostFree(b->h_active);

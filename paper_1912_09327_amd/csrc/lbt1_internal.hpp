@@ -19,7 +19,8 @@ struct StepKernel {
 const StepKernel *step_kernels(int *count);
 const void *reduce_partial_kernel(int prec);
 const void *reduce_final_kernel();
-const void *batch_step_kernel(int prec, int vec_class);
+const void *batch_step_kernel(int prec, int vec_class, int rows);
 const void *batch_reduce_kernel(int prec);
+const void *batch_reduce_final_kernel();
 
 }  // namespace lbt1

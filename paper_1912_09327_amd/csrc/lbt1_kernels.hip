@@ -25,11 +25,11 @@ __global__ void __launch_bounds__(64) k_reduce_final(const double *partials, int
   {P, HW, W, KIND_STRIP, V, R, (const void *)&k_step_strip<P, HW, W, V, R>, \
    "k_step_strip<" #P "," #HW "," #W "," #V "," #R ">"}
 #define STRIP_WALLS(P, V, R) STRIP(P, false, 0, V, R), STRIP(P, true, 0, V, R), STRIP(P, true, 1, V, R)
-#define STRIP_ROWS(P, V) STRIP_WALLS(P, V, 14), STRIP_WALLS(P, V, 30)
+#define STRIP_ROWS(P, V) STRIP_WALLS(P, V, 6), STRIP_WALLS(P, V, 14)
 // 8 columns per lane only without walls: the wall-aware variants at that width
 // need more registers than a wavefront has and spill (the build refuses any
 // kernel that spills or uses scratch memory)
-#define STRIP_ROWS_NOWALL(P, V) STRIP(P, false, 0, V, 14), STRIP(P, false, 0, V, 30)
+#define STRIP_ROWS_NOWALL(P, V) STRIP(P, false, 0, V, 6), STRIP(P, false, 0, V, 14)
 #define GATHER_ALL(P) GATHER(P, false, 0), GATHER(P, true, 0), GATHER(P, true, 1)
 
 static const StepKernel kTable[] = {
@@ -57,22 +57,32 @@ const void *reduce_partial_kernel(int prec) {
 
 const void *reduce_final_kernel() { return (const void *)&k_reduce_final; }
 
-// Batched kernels (always wall-aware): [precision][vec class 0..2 = vec 1, 2, 4];
-// strips of 14 rows.
-#define BATCH_ROW(P) \
-  {(const void *)&k_step_batch<P, 1, 14>, (const void *)&k_step_batch<P, 2, 14>, (const void *)&k_step_batch<P, 4, 14>, nullptr}
+// Batched kernels (always wall-aware): [precision][vec class 0..2 = vec 1, 2, 4]
+// for strips of 14 rows (tall) and 6 rows (short: half the serial latency of a
+// strip, for classes with too few strips to fill the device).
+#define BATCH_ROW(P, R) \
+  {(const void *)&k_step_batch<P, 1, R>, (const void *)&k_step_batch<P, 2, R>, (const void *)&k_step_batch<P, 4, R>, nullptr}
 
-const void *batch_step_kernel(int prec, int vec_class) {
-  static const void *table[4][4] = {
+const void *batch_step_kernel(int prec, int vec_class, int rows) {
+  static const void *tall[4][4] = {
       {(const void *)&k_step_batch<P_F64, 1, 14>, (const void *)&k_step_batch<P_F64, 2, 14>, nullptr, nullptr},
-      {(const void *)&k_step_batch<P_F32, 1, 14>, (const void *)&k_step_batch<P_F32, 2, 14>,
-       (const void *)&k_step_batch<P_F32, 4, 14>, nullptr},
-      BATCH_ROW(P_F16S),
-      BATCH_ROW(P_BF16S),
+      BATCH_ROW(P_F32, 14),
+      BATCH_ROW(P_F16S, 14),
+      BATCH_ROW(P_BF16S, 14),
+  };
+  static const void *shrt[4][4] = {
+      {(const void *)&k_step_batch<P_F64, 1, 6>, (const void *)&k_step_batch<P_F64, 2, 6>, nullptr, nullptr},
+      BATCH_ROW(P_F32, 6),
+      BATCH_ROW(P_F16S, 6),
+      BATCH_ROW(P_BF16S, 6),
   };
   if (prec < 0 || prec > 3 || vec_class < 0 || vec_class > 3) return nullptr;
-  return table[prec][vec_class];
+  if (rows == 14) return tall[prec][vec_class];
+  if (rows == 6) return shrt[prec][vec_class];
+  return nullptr;
 }
+
+const void *batch_reduce_final_kernel() { return (const void *)&k_reduce_batch_final; }
 
 const void *batch_reduce_kernel(int prec) {
   switch (prec) {

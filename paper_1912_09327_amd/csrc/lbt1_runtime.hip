@@ -241,26 +241,29 @@ static std::tuple<int, int, int, int, int> tune_key(const lbt1_grid *g) {
   return std::make_tuple(g->prec, (int)g->haswall, g->haswall ? g->wall : 0, g->nx, g->ny);
 }
 
-lbt1_kernel_config heuristic_config(int prec, int nx, int ny) {
+// Default without a tuned entry: the gather kernel for tiny grids, else the
+// widest built strip kernel whose chunk divides nx and whose strip is not much
+// wider than the grid, with short strips (6 rows) when tall ones would not give
+// every CU several wavefronts (a strip's rows are walked one after another, so
+// its length sets the latency of a step).
+lbt1_kernel_config heuristic_config(int prec, bool haswall, int wall, int nx, int ny, int cus) {
   lbt1_kernel_config c{};
   if ((long)nx * ny < 64 * 64) {
     c.kernel = LBT1_KERNEL_GATHER;
     return c;
   }
   c.kernel = LBT1_KERNEL_STRIP;
-  c.rows = 14;
   c.waves = 0;
-  const int cands16[] = {8, 4, 2, 1}, cands32[] = {4, 2, 1}, cands64[] = {2, 1};
-  const int *cands = prec == LBT1_F64 ? cands64 : prec == LBT1_F32 ? cands32 : cands16;
-  const int nc = prec == LBT1_F64 ? 2 : prec == LBT1_F32 ? 3 : 4;
   c.vec = 1;
-  for (int i = 0; i < nc; ++i) {
-    const int v = cands[i];
-    if (nx % v == 0 && 64 * v <= std::max(64, nx)) {
+  const int cands[] = {8, 4, 2, 1};
+  for (int v : cands) {
+    if (nx % v == 0 && 62 * v <= std::max(62, nx) && find_kernel(prec, haswall, wall, KIND_STRIP, v, 14)) {
       c.vec = v;
       break;
     }
   }
+  const long tall = (long)((nx / c.vec + 61) / 62) * ((ny + 13) / 14);
+  c.rows = tall < 8L * cus ? 6 : 14;
   return c;
 }
 
@@ -270,7 +273,7 @@ lbt1_status bind_config(lbt1_grid *g, const lbt1_kernel_config &want, int cus) {
   if (c.kernel == LBT1_KERNEL_AUTO) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tuned.find(tune_key(g));
-    c = it != g_tuned.end() ? it->second : heuristic_config(g->prec, g->nx, g->ny);
+    c = it != g_tuned.end() ? it->second : heuristic_config(g->prec, g->haswall, g->wall, g->nx, g->ny, cus);
   }
   const StepKernel *k = nullptr;
   if (c.kernel == LBT1_KERNEL_GATHER) {
@@ -775,7 +778,7 @@ lbt1_status lbt1_autotune(lbt1_grid *g, int32_t steps, int32_t reps, lbt1_kernel
     cands.push_back(c);
   }
   const int vecs[] = {1, 2, 4, 8};
-  const int rows[] = {14, 30};
+  const int rows[] = {6, 14};
   const int waves[] = {0, 8, 16};
   for (int v : vecs)
     for (int r : rows)

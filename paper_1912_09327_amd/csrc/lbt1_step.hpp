@@ -487,11 +487,13 @@ template <int P>
 __global__ void __launch_bounds__(256) k_reduce_batch(BatchReduceArgs b) {
   using T = Traits<P>;
   using S = typename T::S;
-  const int n = *b.nactive;
+  const int n = *b.nitems;
   __shared__ double part[4][6];
-  for (int k = blockIdx.x; k < n; k += gridDim.x) {
-    const int slot = b.active[k];
+  for (int it = blockIdx.x; it < n; it += gridDim.x) {
+    const int2 item = b.items[it];
+    const int slot = item.x;
     const BatchGrid &g = b.grids[slot];
+    if (g.steps_left == 0) continue;  // not stepped in this burst (uniform in the block)
     const int p = (g.parity0 + g.steps_left) & 1;
     const S *c0 = static_cast<const S *>(g.plane[p][0]);
     const S *c1 = static_cast<const S *>(g.plane[p][1]);
@@ -501,7 +503,9 @@ __global__ void __launch_bounds__(256) k_reduce_batch(BatchReduceArgs b) {
     S *n2 = static_cast<S *>(b.snaps[slot * 3 + 2]);
     double acc[6] = {0, 0, 0, 0, 0, 0};
     const long nn = (long)g.nx * g.ny;
-    for (long m = threadIdx.x; m < nn; m += blockDim.x) {
+    const long m0 = (long)item.y * kBatchReduceChunk;
+    const long m1 = min(nn, m0 + kBatchReduceChunk);
+    for (long m = m0 + threadIdx.x; m < m1; m += blockDim.x) {
       const int y = (int)(m / g.nx);
       const int x = (int)(m - (long)y * g.nx);
       const long i = (long)y * g.rs + x;
@@ -542,9 +546,27 @@ __global__ void __launch_bounds__(256) k_reduce_batch(BatchReduceArgs b) {
       const int q = threadIdx.x;
       double v = part[0][q];
       for (int w = 1; w < (int)(blockDim.x >> 6); ++w) v = q == 3 ? __builtin_fmax(v, part[w][q]) : v + part[w][q];
-      b.out[slot * 6 + q] = v;
+      b.partials[(long)it * 6 + q] = v;
     }
     __syncthreads();
+  }
+}
+
+// The partials of each active grid, in item order, into out[slot * 6 + q].
+__global__ void __launch_bounds__(64) k_reduce_batch_final(BatchReduceArgs b) {
+  const int n = *b.nactive;
+  for (int k = blockIdx.x; k < n; k += gridDim.x) {
+    const int slot = b.active[k];
+    const int2 r = b.ranges[slot];
+    const int q = threadIdx.x;
+    if (q < 6) {
+      double v = 0.0;
+      for (int i = 0; i < r.y; ++i) {
+        const double x = b.partials[(long)(r.x + i) * 6 + q];
+        v = q == 3 ? __builtin_fmax(v, x) : v + x;
+      }
+      b.out[slot * 6 + q] = v;
+    }
   }
 }
 

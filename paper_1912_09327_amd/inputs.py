@@ -74,43 +74,55 @@ def channel_force_for(u_max, ny):
     return 8.0 * NU_TAU1 * u_max / (H * H)
 
 
-def porous_channel(L, rng, r_lo=3.0, r_hi=12.0, porosity=0.8, max_tries=20000):
+def porous_channel(L, rng, r_lo=3.0, r_hi=12.0, porosity=0.8, max_tries=200000):
     """Channel with random non-overlapping disks (periodic in x), added one by one
-    until the fluid fraction of the interior drops to ``porosity`` or below.
+    (random sequential addition) until the fluid fraction of the interior drops to
+    ``porosity`` or below.
 
-    Radii U[r_lo, r_hi], capped at L/8.  Returns (flags, periodic, achieved_porosity).
+    Radii U[r_lo, r_hi], capped at L/8; disks keep one node of fluid between them.
+    Returns (flags, periodic, achieved_porosity).
     """
     nx = ny = int(L)
     flags, periodic = channel(nx, ny)
     interior = (ny - 2) * nx
     r_hi = min(r_hi, L / 8.0)
     r_lo = min(r_lo, r_hi)
-    disks = []
-    yy, xx = np.mgrid[0:ny, 0:nx]
+    cell = 2.0 * r_hi + 1.0                    # disks overlapping a candidate sit in adjacent cells
+    ncx = max(1, int(nx // cell))
+    cells = {}
     solid = 0
     tries = 0
-    while solid / interior < 1.0 - porosity and tries < max_tries:
+    while solid < (1.0 - porosity) * interior and tries < max_tries:
         tries += 1
         r = rng.uniform(r_lo, r_hi)
         cx = rng.uniform(0, nx)
         cy = rng.uniform(1 + r, ny - 1 - r) if ny - 2 > 2 * r + 1 else (ny - 1) / 2.0
+        gx, gy = int(cx / nx * ncx) % ncx, int(cy // cell)
         ok = True
-        for (px, py, pr) in disks:
-            dx = abs(cx - px)
-            dx = min(dx, nx - dx)          # periodic in x
-            if math.hypot(dx, cy - py) < r + pr + 1.0:
-                ok = False
+        for dx in (-1, 0, 1):
+            for dy in (-1, 0, 1):
+                for (px, py, pr) in cells.get(((gx + dx) % ncx, gy + dy), ()):
+                    ddx = abs(cx - px)
+                    ddx = min(ddx, nx - ddx)   # periodic in x
+                    if math.hypot(ddx, cy - py) < r + pr + 1.0:
+                        ok = False
+                        break
+                if not ok:
+                    break
+            if not ok:
                 break
         if not ok:
             continue
-        disks.append((cx, cy, r))
-        dx = np.abs(xx - cx)
-        dx = np.minimum(dx, nx - dx)
-        inside = (dx ** 2 + (yy - cy) ** 2) <= r * r
-        inside[0, :] = False
-        inside[-1, :] = False
-        flags[inside] = SOLID
-        solid = int((flags[1:-1] == SOLID).sum())
+        cells.setdefault((gx, gy), []).append((cx, cy, r))
+        y0, y1 = max(1, int(math.floor(cy - r))), min(ny - 2, int(math.ceil(cy + r)))
+        x0, x1 = int(math.floor(cx - r)), int(math.ceil(cx + r))
+        yy, xx = np.mgrid[y0:y1 + 1, x0:x1 + 1]
+        inside = (xx - cx) ** 2 + (yy - cy) ** 2 <= r * r
+        xs = np.mod(xx[inside], nx)
+        ys = yy[inside]
+        newly = flags[ys, xs] != SOLID
+        solid += int(newly.sum())
+        flags[ys, xs] = SOLID
     return flags, periodic, 1.0 - solid / interior
 
 

@@ -18,6 +18,7 @@ The scheduling logic talks to a ``Backend`` (``GpuBackend`` here); the tests
 drive it with a CPU stand-in.
 """
 import collections
+import concurrent.futures
 import time
 from dataclasses import dataclass, field
 
@@ -73,7 +74,7 @@ class Backend:
     def grid_bytes(self, req):          # device bytes the request's grid takes
         raise NotImplementedError
 
-    def create(self, req):              # build the grid and its geometry; returns a handle
+    def create(self, req, geo=None):    # the grid with geometry `geo` (built if None); a handle
         raise NotImplementedError
 
     def admit(self, handle, step_budget, tol):   # slot id, or None if the engine is full
@@ -120,9 +121,9 @@ class GpuBackend(Backend):
     def grid_bytes(self, req):
         return self.C.grid_bytes(req.L, req.L, self.C.PRECISIONS[self.prec], self.C.OPT_SNAPSHOT)
 
-    def create(self, req):
+    def create(self, req, geo=None):
         from .grid import Grid
-        flags, rho, jx, jy, periodic, force = geometry(req)
+        flags, rho, jx, jy, periodic, force = geo if geo is not None else geometry(req)
         g = Grid(req.L, req.L, prec=self.prec, wall=self.wall, periodic=periodic, force=force,
                  scale=self.scale)
         g.set_geometry(flags, rho, jx, jy)
@@ -183,7 +184,7 @@ class Server:
     """Continuous batching with admission by HBM budget and slot count."""
 
     def __init__(self, backend, hbm_budget_bytes, max_slots, burst=100, keep_results=False, clock=None,
-                 sleep=None):
+                 sleep=None, progress=None):
         self.b = backend
         self.budget = int(hbm_budget_bytes)
         self.max_slots = int(max_slots)
@@ -191,6 +192,7 @@ class Server:
         self.keep = keep_results
         self.clock = clock or time.perf_counter
         self.sleep = sleep or time.sleep
+        self.progress = progress       # optional callable(done_count, now)
 
     def serve(self, requests):
         """Serve `requests` (arrival times relative to the call); returns the Results
@@ -200,11 +202,16 @@ class Server:
         active = {}                    # slot -> (request, handle, admitted, bytes)
         used = 0
         done = []
+        # geometry of queued requests is built on a host thread while the GPU steps
+        pool = concurrent.futures.ThreadPoolExecutor(max_workers=2)
+        geo = {}
         t0 = self.clock()
         while pending or queue or active:
             now = self.clock() - t0
             while pending and pending[0].arrival <= now:
-                queue.append(pending.popleft())
+                req = pending.popleft()
+                queue.append(req)
+                geo[req.id] = pool.submit(geometry, req)
             # admit in arrival order while the head fits (no overtaking, so no starvation)
             while queue and len(active) < self.max_slots:
                 req = queue[0]
@@ -213,7 +220,7 @@ class Server:
                     raise ValueError(f"request {req.id} needs {nbytes} B, more than the whole budget")
                 if used + nbytes > self.budget:
                     break
-                handle = self.b.create(req)
+                handle = self.b.create(req, geo.pop(req.id).result())
                 slot = self.b.admit(handle, req.steps, req.tol)
                 if slot is None:       # the engine's own accounting disagrees: wait
                     self.b.release(handle)
@@ -232,38 +239,51 @@ class Server:
                                        float(steps) * self.b.fluid_nodes(handle), mom))
                     self.b.release(handle)
                     used -= nbytes
+                    if self.progress:
+                        self.progress(len(done), now)
             elif pending:
                 wait = pending[0].arrival - (self.clock() - t0)
                 if wait > 0:
                     self.sleep(min(wait, 0.05))
+        pool.shutdown()
         return done
 
 
 class PlainFifo:
     """One request at a time, in arrival order, one launch per step."""
 
-    def __init__(self, backend, burst=100, keep_results=False, clock=None, sleep=None):
+    def __init__(self, backend, burst=100, keep_results=False, clock=None, sleep=None, progress=None):
         self.b = backend
         self.burst = int(burst)
         self.keep = keep_results
         self.clock = clock or time.perf_counter
         self.sleep = sleep or time.sleep
+        self.progress = progress
 
     def serve(self, requests):
         done = []
+        order = sorted(requests, key=lambda r: r.arrival)
+        pool = concurrent.futures.ThreadPoolExecutor(max_workers=1)
+        nxt = pool.submit(geometry, order[0]) if order else None
         t0 = self.clock()
-        for req in sorted(requests, key=lambda r: r.arrival):
+        for k, req in enumerate(order):
             now = self.clock() - t0
             if req.arrival > now:
                 self.sleep(req.arrival - now)
             adm = self.clock() - t0
-            handle = self.b.create(req)
+            g = nxt.result()
+            # the next request's geometry is built while this one runs
+            nxt = pool.submit(geometry, order[k + 1]) if k + 1 < len(order) else None
+            handle = self.b.create(req, g)
             state, steps, res = self.b.run_alone(handle, req.steps, req.tol, self.burst)
             now = self.clock() - t0
             mom = self.b.read(handle) if self.keep else None
             done.append(Result(req.id, req.arrival, adm, now, steps, state, res,
                                float(steps) * self.b.fluid_nodes(handle), mom))
             self.b.release(handle)
+            if self.progress:
+                self.progress(len(done), now)
+        pool.shutdown()
         return done
 
 

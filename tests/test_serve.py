@@ -36,8 +36,8 @@ class OracleBackend(Backend):
     def grid_bytes(self, req):
         return req.L * req.L * self.BYTES_PER_NODE
 
-    def create(self, req):
-        flags, rho, jx, jy, per, F = geometry(req)
+    def create(self, req, geo=None):
+        flags, rho, jx, jy, per, F = geo if geo is not None else geometry(req)
         n = req.L
         rho = np.ones((n, n)) if rho is None else rho
         jx = np.zeros((n, n)) if jx is None else jx

@@ -101,7 +101,7 @@ def test_every_node_written_once_and_all_accesses_in_bounds(nx, ny, periodic):
         for VEC in vecs:
             if nx % VEC:
                 continue
-            for NY in (14, 30):
+            for NY in (6, 14):
                 for waves in (0, 8):
                     written, nch = run_model(nx, ny, c, VEC, NY, waves, periodic)
                     assert len(written) == 3 * ny * nch, (nx, ny, VEC, NY, waves)
