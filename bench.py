@@ -142,8 +142,8 @@ def cpu_baseline(state, budget_s):
     sub = [np.ascontiguousarray(a[:m, :m]) for a in state]
     oracle.run(*sub, 1, None, 3)                  # warm the thread pool
     t0 = time.perf_counter()
-    oracle.run(*sub, 3, None, 3)
-    one = (time.perf_counter() - t0) / 3
+    oracle.run(*sub, 10, None, 3)
+    one = (time.perf_counter() - t0) / 10
     n = max(1, int(budget_s / max(one, 1e-3)))
     t0 = time.perf_counter()
     oracle.run(*sub, n, None, 3)
@@ -166,6 +166,38 @@ def field_error(a, ref):
     return out
 
 
+ACC_STEPS = (1, 10, 100, 1000)
+ACC_WINDOW = (3072, 3072, 2048, 2048)      # x0, y0, w, h of the sampled window
+
+
+def accuracy(n, state, storages):
+    """Error of each storage format against the FP64 run after 1, 10, 100 and 1000
+    steps from the same start, on a 2048 x 2048 window of the grid (untimed)."""
+    from paper_1912_09327_amd.grid import Grid
+    x0, y0, w, h = ACC_WINDOW
+    if n < x0 + w:
+        x0 = y0 = 0
+        w = h = n
+    snaps = {}
+    for storage in ["f64"] + [s for s in storages if s != "f64"]:
+        g = Grid(n, n, prec=storage, periodic=3)
+        try:
+            g.set_geometry(None, *state)
+            done = 0
+            for k in ACC_STEPS:
+                g.step(k - done)
+                done = k
+                snaps[(storage, k)] = g.read_window(x0, y0, w, h)
+        finally:
+            g.close()
+    out = {}
+    for storage in storages:
+        if storage == "f64":
+            continue
+        out[storage] = {str(k): field_error(snaps[(storage, k)], snaps[("f64", k)]) for k in ACC_STEPS}
+    return out, f"{w}x{h} window at ({x0}, {y0})"
+
+
 def run_periodic(args, torch):
     from paper_1912_09327_amd import inputs as I
     n = args.n
@@ -175,8 +207,6 @@ def run_periodic(args, torch):
     results = {}
     order = [args.storage] + ([] if args.no_variants else
                               [s for s in ("f64", "f32", "f16s", "bf16s") if s != args.storage])
-    ref_fields = None
-    fields = {}
     for storage in order:
         log(f"[bench] {storage}: set_geometry + autotune")
         g = make_grid(n, storage, state, tune=not args.no_tune, kernel=args.kernel, planar=args.planar)
@@ -189,13 +219,8 @@ def run_periodic(args, torch):
                                 kernel_ms=kms, achieved=achieved, kernel=kname, config=cfg)
         log(f"[bench] {storage}: {results[storage]['mlups']:.0f} MLUPS, kernel {kms:.4f} ms, "
             f"{achieved:.0f} GB/s")
-        if not args.no_variants:
-            # every variant has now taken warmup + steps steps from the same start
-            fields[storage] = g.read_moments()
         g.close()
         torch.cuda.empty_cache()
-    if "f64" in fields:
-        ref_fields = fields["f64"]
     head = results[args.storage]
     c = VALUE_BYTES[args.storage]
     line = {
@@ -232,13 +257,16 @@ def run_periodic(args, torch):
     except Exception as e:  # pragma: no cover - measurement aid only
         log(f"[bench] copy ceiling failed: {e}")
     if not args.no_variants:
+        log("[bench] accuracy of the storage formats against FP64 (untimed)")
+        err, where = accuracy(n, state, list(results))
+        torch.cuda.empty_cache()
         var = {}
         for s, r in results.items():
             v = dict(mlups=round(r["mlups"], 1), achieved_GBps=round(r["achieved"], 1),
                      frac=round(r["achieved"] / HBM_PEAK_GBPS, 4), kernel=r["kernel"])
-            if ref_fields is not None and s != "f64":
-                v["error_vs_f64"] = field_error(fields[s], ref_fields)
-                v["error_vs_f64"]["after_steps"] = args.warmup + args.steps
+            if s in err:
+                v["error_vs_f64"] = dict(err[s], sample=where,
+                                         normalised_by="rms of the FP64 field at the same step")
             var[s] = v
         line["variants"] = var
     if not args.no_cpu:

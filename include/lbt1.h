@@ -147,6 +147,14 @@ lbt1_status lbt1_step(lbt1_grid *g, int64_t n);
  * (any of them may be NULL).  Synchronises the grid's stream. */
 lbt1_status lbt1_read_moments(lbt1_grid *g, double *rho, double *jx, double *jy);
 
+/* Copy the moments of the window x0 <= x < x0+w, y0 <= y < y0+h into h*w host
+ * arrays (row-major, x fastest; any of them may be NULL).  Used for point
+ * probes of large grids: the centre-velocity and mid-section flux stopping
+ * rules of section 3, and sampled checks.  EINVAL if the window is empty or
+ * not inside the grid.  Synchronises the grid's stream. */
+lbt1_status lbt1_read_window(lbt1_grid *g, int32_t x0, int32_t y0, int32_t w, int32_t h, double *rho, double *jx,
+                             double *jy);
+
 /* FP64 diagnostics over FLUID nodes, see LBT1_REDUCE_*; out has
  * LBT1_REDUCE_SLOTS doubles, slots not asked for are left untouched except
  * out[5].  Synchronises the grid's stream. */

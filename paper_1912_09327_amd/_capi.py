@@ -70,6 +70,7 @@ SIGNATURES = {
     "lbt1_set_geometry": (ctypes.c_int, [_vp, _u8p, _dp, _dp, _dp]),
     "lbt1_step": (ctypes.c_int, [_vp, ctypes.c_int64]),
     "lbt1_read_moments": (ctypes.c_int, [_vp, _dp, _dp, _dp]),
+    "lbt1_read_window": (ctypes.c_int, [_vp, _i32, _i32, _i32, _i32, _dp, _dp, _dp]),
     "lbt1_reduce": (ctypes.c_int, [_vp, ctypes.c_uint32, _dp]),
     "lbt1_sync": (ctypes.c_int, [_vp]),
     "lbt1_destroy_grid": (ctypes.c_int, [_vp]),

@@ -642,15 +642,18 @@ lbt1_status lbt1_sync(lbt1_grid *g) {
   return LBT1_OK;
 }
 
-lbt1_status lbt1_read_moments(lbt1_grid *g, double *rho, double *jx, double *jy) {
+lbt1_status lbt1_read_window(lbt1_grid *g, int32_t x0, int32_t y0, int32_t w, int32_t h, double *rho, double *jx,
+                             double *jy) {
   clear_error();
   if (!g) return fail(LBT1_EINVAL, "null grid");
   if (!g->geometry) return fail(LBT1_ESTATE, "no geometry set");
-  const int nx = g->nx, ny = g->ny;
+  if (w <= 0 || h <= 0 || x0 < 0 || y0 < 0 || (int64_t)x0 + w > g->nx || (int64_t)y0 + h > g->ny)
+    return fail(LBT1_EINVAL, "window (%d, %d) + %d x %d is not inside the %d x %d grid", x0, y0, w, h, g->nx, g->ny);
   const size_t c = value_bytes(g->prec);
+  const size_t n = (size_t)w * h;
   std::vector<char> stage;
   try {
-    stage.resize((size_t)nx * ny * c);
+    stage.resize(n * c);
   } catch (...) {
     return fail(LBT1_ENOMEM, "host staging");
   }
@@ -660,14 +663,23 @@ lbt1_status lbt1_read_moments(lbt1_grid *g, double *rho, double *jx, double *jy)
   for (int q = 0; q < 3; ++q) {
     double *dst = q == 0 ? rho : q == 1 ? jx : jy;
     if (!dst) continue;
-    if ((e = hipMemcpy2D(stage.data(), (size_t)nx * c, g->plane[g->parity][q], (size_t)g->L.rs * c, (size_t)nx * c, ny,
+    const char *src = (const char *)g->plane[g->parity][q] + ((size_t)y0 * g->L.rs + x0) * c;
+    if ((e = hipMemcpy2D(stage.data(), (size_t)w * c, src, (size_t)g->L.rs * c, (size_t)w * c, h,
                          hipMemcpyDeviceToHost)) != hipSuccess)
       return hip_fail(e, "hipMemcpy2D D2H");
-    decode_values(g->prec, stage.data(), (size_t)nx * ny, g->sc[q == 0 ? 0 : 1], dst);
+    decode_values(g->prec, stage.data(), n, g->sc[q == 0 ? 0 : 1], dst);
     if (q == 0)
-      for (size_t i = 0; i < (size_t)nx * ny; ++i) dst[i] += 1.0;
+      for (size_t i = 0; i < n; ++i) dst[i] += 1.0;
   }
   return LBT1_OK;
+}
+
+lbt1_status lbt1_read_moments(lbt1_grid *g, double *rho, double *jx, double *jy) {
+  if (!g) {
+    clear_error();
+    return fail(LBT1_EINVAL, "null grid");
+  }
+  return lbt1_read_window(g, 0, 0, g->nx, g->ny, rho, jx, jy);
 }
 
 lbt1_status lbt1_reduce(lbt1_grid *g, uint32_t what, double *out) {

@@ -87,6 +87,14 @@ class Grid:
         C.check(C.lib.lbt1_read_moments(self.handle, _dptr(rho), _dptr(jx), _dptr(jy)))
         return rho, jx, jy
 
+    def read_window(self, x0, y0, w, h):
+        """(rho, jx, jy) of the window x0 <= x < x0+w, y0 <= y < y0+h, each [h, w]."""
+        shape = (int(h), int(w))
+        rho, jx, jy = np.empty(shape), np.empty(shape), np.empty(shape)
+        C.check(C.lib.lbt1_read_window(self.handle, int(x0), int(y0), int(w), int(h),
+                                       _dptr(rho), _dptr(jx), _dptr(jy)))
+        return rho, jx, jy
+
     def reduce(self, what=C.REDUCE_ALL):
         out = np.full(C.REDUCE_SLOTS, np.nan)
         C.check(C.lib.lbt1_reduce(self.handle, int(what), _dptr(out)))
