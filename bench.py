@@ -11,8 +11,10 @@ HIP-graph bursts.  Inputs are resident in HBM before the timed region.
 The JSON line carries:
   value        fluid lattice updates per second (MLUPS), whole job
   roofline     the step kernel's algorithmic HBM bytes per launch (read and write
-               3 moment planes: 2 * 3 * c bytes per fluid node) over its average
-               launch duration from HIP events on the grid's stream, against 8 TB/s
+               3 moment planes once: 2 * 3 * c bytes per fluid node, for one step,
+               or for two when the kernel fuses two steps per pass) over its
+               average launch duration from HIP events on the grid's stream,
+               against 8 TB/s
   cpu_baseline the FP64 CPU oracle on a bounded sample of the same workload
   variants     the same run with FP64, FP16 and BF16 shifted storage, each with its
                error against the FP64 run
@@ -53,7 +55,7 @@ def parse():
     p.add_argument("--no-variants", action="store_true", help="skip the other storage variants")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--no-tune", action="store_true", help="skip the autotuner")
-    p.add_argument("--kernel", default=None, help="fix the kernel: gather or strip:vec:rows:waves")
+    p.add_argument("--kernel", default=None, help="fix the kernel: gather or strip:vec:rows:waves[:fuse]")
     p.add_argument("--planar", action="store_true", help="three separate moment planes instead of "
                    "the row-interleaved layout")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -73,8 +75,10 @@ def make_grid(n, storage, state, tune=True, kernel=None, planar=False):
         if kernel == "gather":
             g.set_kernel("gather")
         else:
-            _, v, r, w = kernel.split(":")
-            g.set_kernel("strip", int(v), int(r), int(w))
+            parts = kernel.split(":")
+            v, r, w = parts[1:4]
+            f = parts[4] if len(parts) > 4 else 1
+            g.set_kernel("strip", int(v), int(r), int(w), int(f))
     elif tune:
         g.autotune(steps=10, reps=2)
     return g
@@ -125,7 +129,7 @@ def measured_traffic(storage, kernel_name, kernel_ms):
     except (OSError, KeyError, ValueError):
         return None
     h = hashlib.sha256()
-    for f in ("lbt1_step.hpp", "lbt1_device.hpp", "lbt1_args.hpp", "lbt1_kernels.hip"):
+    for f in ("lbt1_step.hpp", "lbt1_fused.hpp", "lbt1_device.hpp", "lbt1_args.hpp", "lbt1_kernels.hip"):
         h.update(open(os.path.join(ROOT, "paper_1912_09327_amd", "csrc", f), "rb").read())
     if rec.get("source_hash") != h.hexdigest()[:16] or rec.get("kernel_bench") != kernel_name:
         return None
@@ -214,10 +218,14 @@ def run_periodic(args, torch):
         log(f"[bench] {storage}: kernel {kname} {cfg}")
         wall, kms = timed_run(g, args.steps, args.warmup, torch)
         c = VALUE_BYTES[storage]
-        achieved = 2 * 3 * c * lups / (kms * 1e-3) / 1e9
+        K = max(1, cfg.get("fuse", 1)) if cfg.get("kernel") == 2 else 1   # steps per launch
+        launch_ms = kms * K
+        achieved = 2 * 3 * c * lups / (launch_ms * 1e-3) / 1e9
         results[storage] = dict(mlups=lups * args.steps / wall / 1e6, ms_per_step=wall * 1e3 / args.steps,
-                                kernel_ms=kms, achieved=achieved, kernel=kname, config=cfg)
-        log(f"[bench] {storage}: {results[storage]['mlups']:.0f} MLUPS, kernel {kms:.4f} ms, "
+                                kernel_ms=launch_ms, steps_per_launch=K, achieved=achieved, kernel=kname,
+                                config=cfg)
+        log(f"[bench] {storage}: {results[storage]['mlups']:.0f} MLUPS, launch {launch_ms:.4f} ms "
+            f"({K} step(s)), "
             f"{achieved:.0f} GB/s")
         g.close()
         torch.cuda.empty_cache()
@@ -242,7 +250,10 @@ def run_periodic(args, torch):
                    "reduction_every": 100, "kernel": head["kernel"], "kernel_config": head["config"]},
         "roofline": {"bound": "hbm", "achieved": round(head["achieved"], 1), "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": round(head["achieved"] / HBM_PEAK_GBPS, 4), "traffic": None,
-                     "bytes_per_lup": 2 * 3 * c, "kernel_ms": round(head["kernel_ms"], 5)},
+                     "bytes_per_launch": 2 * 3 * c * int(lups), "steps_per_launch": head["steps_per_launch"],
+                     "bytes_per_lup": round(2 * 3 * c / head["steps_per_launch"], 3),
+                     "kernel_ms": round(head["kernel_ms"], 5),
+                     "single_step_equivalent_GBps": round(2 * 3 * c * head["mlups"] * 1e6 / 1e9, 1)},
     }
     tr = measured_traffic(args.storage, head["kernel"], head["kernel_ms"])
     if tr is not None:

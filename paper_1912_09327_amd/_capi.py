@@ -52,10 +52,10 @@ class GridDesc(ctypes.Structure):
 
 class KernelConfig(ctypes.Structure):
     _fields_ = [("kernel", ctypes.c_int32), ("vec", ctypes.c_int32), ("rows", ctypes.c_int32),
-                ("waves", ctypes.c_int32)]
+                ("waves", ctypes.c_int32), ("fuse", ctypes.c_int32)]
 
     def as_dict(self):
-        return dict(kernel=self.kernel, vec=self.vec, rows=self.rows, waves=self.waves)
+        return dict(kernel=self.kernel, vec=self.vec, rows=self.rows, waves=self.waves, fuse=self.fuse)
 
 
 _vp = ctypes.c_void_p

@@ -14,6 +14,7 @@ struct StepKernel {
   int prec, haswall, wall, kind, vec, rows;
   const void *fn;
   const char *name;
+  int steps;  // time steps one launch advances (fused strip kernels: 2 or 4)
 };
 
 const StepKernel *step_kernels(int *count);

@@ -1,6 +1,7 @@
 // Instantiation of the step and reduction kernels and the table the runtime
 // selects from.
 #include "lbt1_internal.hpp"
+#include "lbt1_fused.hpp"
 #include "lbt1_step.hpp"
 
 namespace lbt1 {
@@ -20,10 +21,15 @@ __global__ void __launch_bounds__(64) k_reduce_final(const double *partials, int
 #define LBT1_STR(x) LBT1_STR2(x)
 
 #define GATHER(P, HW, W) \
-  {P, HW, W, KIND_GATHER, 0, 0, (const void *)&k_step_gather<P, HW, W>, "k_step_gather<" #P "," #HW "," #W ">"}
+  {P, HW, W, KIND_GATHER, 0, 0, (const void *)&k_step_gather<P, HW, W>, "k_step_gather<" #P "," #HW "," #W ">", 1}
 #define STRIP(P, HW, W, V, R)                                                    \
   {P, HW, W, KIND_STRIP, V, R, (const void *)&k_step_strip<P, HW, W, V, R>, \
-   "k_step_strip<" #P "," #HW "," #W "," #V "," #R ">"}
+   "k_step_strip<" #P "," #HW "," #W "," #V "," #R ">", 1}
+// K steps per launch, fully periodic grids without wall or fixed nodes
+#define FUSED(P, V, R, K)                                                        \
+  {P, false, 0, KIND_STRIP, V, R, (const void *)&k_step_fused<P, V, R, K>, \
+   "k_step_fused<" #P "," #V "," #R "," #K ">", K}
+#define FUSED_ROWS(P, V, K) FUSED(P, V, 6, K), FUSED(P, V, 14, K)
 #define STRIP_WALLS(P, V, R) STRIP(P, false, 0, V, R), STRIP(P, true, 0, V, R), STRIP(P, true, 1, V, R)
 #define STRIP_ROWS(P, V) STRIP_WALLS(P, V, 6), STRIP_WALLS(P, V, 14)
 // 8 columns per lane only without walls: the wall-aware variants at that width
@@ -38,6 +44,10 @@ static const StepKernel kTable[] = {
     STRIP_ROWS(P_F32, 4),  STRIP_ROWS(P_F16S, 1), STRIP_ROWS(P_F16S, 2), STRIP_ROWS(P_F16S, 4),
     STRIP_ROWS_NOWALL(P_F16S, 8), STRIP_ROWS(P_BF16S, 1), STRIP_ROWS(P_BF16S, 2), STRIP_ROWS(P_BF16S, 4),
     STRIP_ROWS_NOWALL(P_BF16S, 8),
+    // two steps per launch; four would need more registers than a wavefront has
+    FUSED_ROWS(P_F64, 2, 2),   FUSED_ROWS(P_F32, 2, 2),   FUSED_ROWS(P_F32, 4, 2),
+    FUSED_ROWS(P_F16S, 2, 2),  FUSED_ROWS(P_F16S, 4, 2),  FUSED_ROWS(P_BF16S, 2, 2),
+    FUSED_ROWS(P_BF16S, 4, 2),
 };
 
 const StepKernel *step_kernels(int *count) {

@@ -221,14 +221,14 @@ static lbt1_status check_device(int *dev_out, int *cus) {
 // ----------------------------------------------------------------- kernel selection
 static bool strip_fits(int nx, int vec) { return vec >= 1 && nx % vec == 0; }
 
-const StepKernel *find_kernel(int prec, bool haswall, int wall, int kind, int vec, int rows) {
+const StepKernel *find_kernel(int prec, bool haswall, int wall, int kind, int vec, int rows, int fuse) {
   int n = 0;
   const StepKernel *t = step_kernels(&n);
   for (int i = 0; i < n; ++i) {
     const StepKernel &k = t[i];
     if (k.prec != prec || k.kind != kind || (k.haswall != 0) != haswall) continue;
     if (haswall && k.wall != wall) continue;
-    if (kind == KIND_STRIP && (k.vec != vec || k.rows != rows)) continue;
+    if (kind == KIND_STRIP && (k.vec != vec || k.rows != rows || k.steps != fuse)) continue;
     return &k;
   }
   return nullptr;
@@ -255,9 +255,25 @@ lbt1_kernel_config heuristic_config(int prec, bool haswall, int wall, int nx, in
   c.kernel = LBT1_KERNEL_STRIP;
   c.waves = 0;
   c.vec = 1;
+  c.fuse = 1;
+  if (!haswall) {
+    // two steps per pass (measured fastest on large periodic grids): 4 columns per
+    // lane in FP32, 2 in FP64 (registers) and in 16-bit storage (arithmetic-bound)
+    const int v = prec == LBT1_F32 ? 4 : 2;
+    if (nx % v == 0 && 62 * v <= std::max(62, nx)) {
+      const long tall = (long)((nx / v + 61) / 62) * ((ny + 13) / 14);
+      const int r = (prec == LBT1_F16S || prec == LBT1_BF16S) && tall >= 8L * cus ? 14 : 6;
+      if (find_kernel(prec, false, 0, KIND_STRIP, v, r, 2)) {
+        c.vec = v;
+        c.rows = r;
+        c.fuse = 2;
+        return c;
+      }
+    }
+  }
   const int cands[] = {8, 4, 2, 1};
   for (int v : cands) {
-    if (nx % v == 0 && 62 * v <= std::max(62, nx) && find_kernel(prec, haswall, wall, KIND_STRIP, v, 14)) {
+    if (nx % v == 0 && 62 * v <= std::max(62, nx) && find_kernel(prec, haswall, wall, KIND_STRIP, v, 14, 1)) {
       c.vec = v;
       break;
     }
@@ -275,20 +291,28 @@ lbt1_status bind_config(lbt1_grid *g, const lbt1_kernel_config &want, int cus) {
     auto it = g_tuned.find(tune_key(g));
     c = it != g_tuned.end() ? it->second : heuristic_config(g->prec, g->haswall, g->wall, g->nx, g->ny, cus);
   }
-  const StepKernel *k = nullptr;
+  const StepKernel *k = nullptr, *k1 = nullptr;
   if (c.kernel == LBT1_KERNEL_GATHER) {
-    k = find_kernel(g->prec, g->haswall, g->wall, KIND_GATHER, 0, 0);
+    k = k1 = find_kernel(g->prec, g->haswall, g->wall, KIND_GATHER, 0, 0, 1);
     c.vec = c.rows = c.waves = 0;
+    c.fuse = 1;
   } else if (c.kernel == LBT1_KERNEL_STRIP) {
     if (!strip_fits(g->nx, c.vec))
       return fail(LBT1_EINVAL, "strip kernel: vec %d does not divide nx %d", c.vec, g->nx);
     if (c.waves < 0 || c.waves > 32) return fail(LBT1_EINVAL, "waves %d out of range", c.waves);
-    k = find_kernel(g->prec, g->haswall, g->wall, KIND_STRIP, c.vec, c.rows);
+    if (c.fuse == 0) c.fuse = 1;
+    if (c.fuse < 1 || c.fuse > c.vec) return fail(LBT1_EINVAL, "fuse %d must be between 1 and vec %d", c.fuse, c.vec);
+    if (c.fuse > 1 && g->haswall)
+      return fail(LBT1_EINVAL, "fused steps need a grid periodic in x and y without SOLID or FIXED nodes");
+    k = find_kernel(g->prec, g->haswall, g->wall, KIND_STRIP, c.vec, c.rows, c.fuse);
+    k1 = find_kernel(g->prec, g->haswall, g->wall, KIND_STRIP, c.vec, c.rows, 1);
   } else {
     return fail(LBT1_EINVAL, "unknown kernel family %d", c.kernel);
   }
-  if (!k) return fail(LBT1_EINVAL, "no built kernel for vec %d rows %d at this precision", c.vec, c.rows);
+  if (!k || !k1)
+    return fail(LBT1_EINVAL, "no built kernel for vec %d rows %d fuse %d at this precision", c.vec, c.rows, c.fuse);
   g->kern = k;
+  g->kern1 = k1;
   g->cfg = c;
   g->cfg.kernel = k->kind == KIND_GATHER ? LBT1_KERNEL_GATHER : LBT1_KERNEL_STRIP;
   if (k->kind == KIND_GATHER) {
@@ -340,19 +364,22 @@ StepArgs step_args(const lbt1_grid *g, int src_parity) {
   return a;
 }
 
-hipError_t launch_step(lbt1_grid *g, int src_parity, hipStream_t s) {
+// One launch of kernel k (g->kern, or its single-step companion g->kern1,
+// which has the same launch shape) reading parity src_parity.
+hipError_t launch_step(lbt1_grid *g, const StepKernel *k, int src_parity, hipStream_t s) {
   StepArgs a = step_args(g, src_parity);
-  if (g->kern->kind == KIND_GATHER) {
+  if (k->kind == KIND_GATHER) {
     void *args[] = {&a};
-    return hipLaunchKernel(g->kern->fn, g->grid, g->block, args, 0, s);
+    return hipLaunchKernel(k->fn, g->grid, g->block, args, 0, s);
   }
   StripMap m = g->map;
   void *args[] = {&a, &m};
-  return hipLaunchKernel(g->kern->fn, g->grid, g->block, args, 0, s);
+  return hipLaunchKernel(k->fn, g->grid, g->block, args, 0, s);
 }
 
-// A graph of kBurst step launches starting from parity p (kBurst is even, so
-// the parity after a replay is p again).
+// A graph of launches covering kBurst steps starting from parity p.  A launch
+// advances g->kern->steps steps (1 or 2) and flips the parity once; kBurst /
+// steps is even, so the parity after a replay is p again.
 static const int kBurst = 64;
 
 static lbt1_status build_burst(lbt1_grid *g, int p) {
@@ -360,9 +387,10 @@ static lbt1_status build_burst(lbt1_grid *g, int p) {
   hipError_t e = hipGraphCreate(&graph, 0);
   if (e != hipSuccess) return hip_fail(e, "hipGraphCreate");
   hipGraphNode_t prev = nullptr;
-  std::vector<StepArgs> argv(kBurst);
+  const int launches = kBurst / g->kern->steps;
+  std::vector<StepArgs> argv(launches);
   StripMap m = g->map;
-  for (int s = 0; s < kBurst; ++s) {
+  for (int s = 0; s < launches; ++s) {
     argv[s] = step_args(g, (p + s) & 1);
     void *args_gather[] = {&argv[s]};
     void *args_strip[] = {&argv[s], &m};
@@ -416,8 +444,14 @@ lbt1_status enqueue_steps(lbt1_grid *g, int64_t n, hipStream_t s, bool use_graph
       g->steps += kBurst;
     }
   }
-  for (int64_t i = 0; i < n; ++i) {
-    if ((e = launch_step(g, g->parity, s)) != hipSuccess) return hip_fail(e, "step launch");
+  const int K = g->kern->steps;
+  for (; n >= K; n -= K) {
+    if ((e = launch_step(g, g->kern, g->parity, s)) != hipSuccess) return hip_fail(e, "step launch");
+    g->parity ^= 1;
+    g->steps += K;
+  }
+  for (; n > 0; --n) {
+    if ((e = launch_step(g, g->kern1, g->parity, s)) != hipSuccess) return hip_fail(e, "step launch");
     g->parity ^= 1;
     g->steps += 1;
   }
@@ -792,19 +826,25 @@ lbt1_status lbt1_autotune(lbt1_grid *g, int32_t steps, int32_t reps, lbt1_kernel
   const int vecs[] = {1, 2, 4, 8};
   const int rows[] = {6, 14};
   const int waves[] = {0, 8, 16};
+  const int fuses[] = {1, 2};
   for (int v : vecs)
     for (int r : rows)
-      for (int w : waves) {
-        if (!strip_fits(g->nx, v)) continue;
-        if (!find_kernel(g->prec, g->haswall, g->wall, KIND_STRIP, v, r)) continue;
-        if (64 * v > 2 * std::max(64, g->nx)) continue;
-        lbt1_kernel_config c{};
-        c.kernel = LBT1_KERNEL_STRIP;
-        c.vec = v;
-        c.rows = r;
-        c.waves = w;
-        cands.push_back(c);
-      }
+      for (int w : waves)
+        for (int f : fuses) {
+          if (!strip_fits(g->nx, v)) continue;
+          if (f > 1 && g->haswall) continue;
+          if (!find_kernel(g->prec, g->haswall, g->wall, KIND_STRIP, v, r, f)) continue;
+          if (64 * v > 2 * std::max(64, g->nx)) continue;
+          lbt1_kernel_config c{};
+          c.kernel = LBT1_KERNEL_STRIP;
+          c.vec = v;
+          c.rows = r;
+          c.waves = w;
+          c.fuse = f;
+          cands.push_back(c);
+        }
+  // a whole number of fused launches for every candidate
+  steps = (steps + 1) / 2 * 2;
   double best_ms = 1e300;
   lbt1_kernel_config bc = g->cfg;
   lbt1_status st = LBT1_OK;

@@ -60,7 +60,8 @@ struct lbt1_grid {
   // step kernel
   lbt1_kernel_config cfg{};
   bool user_cfg = false;
-  const lbt1::StepKernel *kern = nullptr;
+  const lbt1::StepKernel *kern = nullptr;   // advances kern->steps steps per launch
+  const lbt1::StepKernel *kern1 = nullptr;  // single-step kernel of the same launch shape
   lbt1::StripMap map{};
   dim3 grid{1, 1, 1}, block{1, 1, 1};
   hipGraphExec_t burst[2] = {nullptr, nullptr};

@@ -105,9 +105,9 @@ class Grid:
         C.check(C.lib.lbt1_sync(self.handle))
 
     # -- kernel choice --------------------------------------------------------------
-    def set_kernel(self, kernel="strip", vec=4, rows=14, waves=0):
+    def set_kernel(self, kernel="strip", vec=4, rows=14, waves=0, fuse=1):
         k = {"auto": C.KERNEL_AUTO, "gather": C.KERNEL_GATHER, "strip": C.KERNEL_STRIP}.get(kernel, kernel)
-        cfg = C.KernelConfig(int(k), int(vec), int(rows), int(waves))
+        cfg = C.KernelConfig(int(k), int(vec), int(rows), int(waves), int(fuse))
         C.check(C.lib.lbt1_set_kernel(self.handle, ctypes.byref(cfg)))
         return self
 

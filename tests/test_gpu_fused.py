@@ -1,0 +1,99 @@
+"""GPU tests of the fused two-step strip kernel (through the C ABI).
+
+Two steps per launch on grids periodic in both axes with no wall or fixed
+nodes.  Every configuration must give the bits of single steps (the gather
+kernel), for odd step counts (a single-step launch finishes them), across
+graph bursts, on grids smaller than a strip and with ragged strips; FP64 is
+also held to the oracle.
+"""
+import numpy as np
+import pytest
+
+from gpu_helpers import JTOL, TOL, field_errors, gpu_run, oracle_run
+from paper_1912_09327_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+BUILT = {"f64": (2,), "f32": (2, 4), "f16s": (2, 4), "bf16s": (2, 4)}
+
+
+def _state(nx, ny, seed):
+    return I.random_state(nx, ny, np.random.default_rng(seed))
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16s", "bf16s"])
+@pytest.mark.parametrize("shape", [(512, 77), (248, 64), (130, 33), (8, 5), (4, 3)])
+def test_fused_bitwise_equals_single_steps(prec, shape):
+    nx, ny = shape
+    rho, jx, jy = _state(nx, ny, 31)
+    F = (1e-5, -2e-6)
+    base = gpu_run(None, rho, jx, jy, 25, prec, "paper", 3, F, kernel=dict(kernel="gather"))
+    for vec in BUILT[prec]:
+        if nx % vec:
+            continue
+        for rows in (6, 14):
+            for waves in (0, 8):
+                cfg = dict(kernel="strip", vec=vec, rows=rows, waves=waves, fuse=2)
+                got = gpu_run(None, rho, jx, jy, 25, prec, "paper", 3, F, kernel=cfg)
+                for a, b in zip(base, got):
+                    assert np.array_equal(a, b), (vec, rows, waves)
+
+
+@pytest.mark.parametrize("prec", ["f32", "f16s"])
+def test_fused_graph_bursts_and_splitting(prec):
+    """Bursts of 64 steps (32 fused launches), odd remainders and split calls."""
+    from paper_1912_09327_amd.grid import Grid
+    nx, ny = 372, 90
+    rho, jx, jy = _state(nx, ny, 5)
+    ref = gpu_run(None, rho, jx, jy, 217, prec, "paper", 3, kernel=dict(kernel="gather"))
+    g = Grid(nx, ny, prec=prec, periodic=3)
+    try:
+        g.set_geometry(None, rho, jx, jy)
+        g.set_kernel("strip", vec=2, rows=14, waves=0, fuse=2)
+        for n in (1, 64, 3, 128, 21):
+            g.step(n)
+        got = g.read_moments()
+    finally:
+        g.close()
+    for a, b in zip(ref, got):
+        assert np.array_equal(a, b)
+
+
+def test_fused_f64_matches_oracle():
+    nx, ny = 260, 70
+    rho, jx, jy = _state(nx, ny, 8)
+    F = (2e-5, 1e-5)
+    ref = oracle_run(None, rho, jx, jy, 40, "paper", 3, F)
+    got = gpu_run(None, rho, jx, jy, 40, "f64", "paper", 3, F,
+                  kernel=dict(kernel="strip", vec=2, rows=6, waves=0, fuse=2))
+    ex, ej = field_errors(got, ref)
+    assert ex <= TOL["f64"] and ej <= JTOL["f64"], (ex, ej)
+
+
+def test_fused_refused_where_it_does_not_apply():
+    from paper_1912_09327_amd import _capi as C
+    from paper_1912_09327_amd.grid import Grid
+    flags, per = I.channel(64, 32)
+    g = Grid(64, 32, prec="f32", periodic=per)
+    try:
+        g.set_geometry(flags)
+        with pytest.raises(C.Lbt1Error) as e:            # walls
+            g.set_kernel("strip", vec=2, rows=6, fuse=2)
+        assert e.value.status == C.EINVAL
+    finally:
+        g.close()
+    g = Grid(64, 32, prec="f32", periodic=3)
+    try:
+        g.set_geometry(None)
+        with pytest.raises(C.Lbt1Error) as e:            # fuse > vec
+            g.set_kernel("strip", vec=1, rows=6, fuse=2)
+        assert e.value.status == C.EINVAL
+        with pytest.raises(C.Lbt1Error) as e:            # not built
+            g.set_kernel("strip", vec=2, rows=6, fuse=4)
+        assert e.value.status == C.EINVAL
+        g.set_kernel("strip", vec=2, rows=6, fuse=2)
+        cfg, name = g.kernel()
+        assert cfg["fuse"] == 2 and "fused" in name
+        g.step(3)
+    finally:
+        g.close()
