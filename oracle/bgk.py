@@ -131,7 +131,85 @@ class BGK:
         new[:, fixed] = feq[:, fixed]
         self.f = new
 
-    def run(self, nsteps):
+    # ------------------------------------------------------------- array form
+    # The same push step written with whole-array operations, for grids too
+    # large for the loops above: the link lists are built once from the same
+    # neighbour rule, and every population takes the same arithmetic, so the
+    # two forms agree bit for bit (tested).
+    def _link_lists(self):
+        if getattr(self, "_links", None) is not None:
+            return self._links
+        ny, nx = self.ny, self.nx
+        jj, ii = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+        src_ok = self.flags != SOLID
+        links = []
+        for k in range(9):
+            ip, jp = ii + EX[k], jj + EY[k]
+            inside = np.ones((ny, nx), bool)
+            if self.periodic & 1:
+                ip = ip % nx
+            else:
+                inside &= (ip >= 0) & (ip < nx)
+            if self.periodic & 2:
+                jp = jp % ny
+            else:
+                inside &= (jp >= 0) & (jp < ny)
+            ipc, jpc = np.clip(ip, 0, nx - 1), np.clip(jp, 0, ny - 1)
+            tflag = np.where(inside, self.flags[jpc, ipc], SOLID)
+            stream = src_ok & (tflag != SOLID) & (tflag != FIXED)
+            bounce = (self.flags == FLUID) & (tflag == SOLID)
+            s_idx = (jj * nx + ii)[stream]
+            t_idx = (jpc * nx + ipc)[stream]
+            b_idx = (jj * nx + ii)[bounce]
+            links.append((s_idx, t_idx, b_idx))
+        self._links = links
+        return links
+
+    def step_arrays(self):
+        rho, jx, jy = self.moments()
+        ux = (jx + self.tau * self.F[0]) / np.where(self.flags == SOLID, 1.0, rho)
+        uy = (jy + self.tau * self.F[1]) / np.where(self.flags == SOLID, 1.0, rho)
+        feq = equilibrium(rho, ux, uy)
+        post = self.f - (self.f - feq) / self.tau
+        fixed = self.flags == FIXED
+        post[:, fixed] = feq[:, fixed]
+        new = np.zeros_like(self.f)
+        rflat = rho.reshape(-1)
+        for k, (s_idx, t_idx, b_idx) in enumerate(self._link_lists()):
+            pk = post[k].reshape(-1)
+            new[k].reshape(-1)[t_idx] = pk[s_idx]
+            q = opposite(k)
+            if self.wall == WALL_PAPER:
+                new[q].reshape(-1)[b_idx] = W[k] * rflat[b_idx]
+            else:
+                new[q].reshape(-1)[b_idx] = pk[b_idx]
+        new[:, fixed] = feq[:, fixed]
+        self.f = new
+
+    def run(self, nsteps, arrays=False):
         for _ in range(int(nsteps)):
-            self.step()
+            if arrays:
+                self.step_arrays()
+            else:
+                self.step()
         return self.moments()
+
+
+def shear_mode(tau, kappa):
+    """Linear theory of the BGK step around rest (rho = 1, u = 0) for a wave
+    exp(i kappa y): the one-step operator is streaming S = diag(exp(-i kappa e_y))
+    after the linearised collision I - (I - E) / tau, with E the linearised
+    equilibrium (E f)_k = w_k (sum f + 3 e_k . sum e f).  Returns the eigenvalue
+    and eigenvector of the shear mode (the one carrying x-momentum), the
+    eigenvector scaled to unit x-momentum.  Test infrastructure: pins the BGK
+    oracle at tau != 1 and, as kappa -> 0, the viscosity (tau - 1/2) / 3 of
+    section 2 (Eq. viscosity)."""
+    E = np.array([[W[k] * (1.0 + 3.0 * (EX[k] * EX[q] + EY[k] * EY[q])) for q in range(9)] for k in range(9)])
+    Cop = np.eye(9) - (np.eye(9) - E) / tau
+    S = np.diag([np.exp(-1j * kappa * EY[k]) for k in range(9)])
+    lam, vec = np.linalg.eig(S @ Cop)
+    ex = np.array(EX, dtype=float)
+    jx = ex @ vec
+    best = int(np.argmax(np.abs(jx) / np.linalg.norm(vec, axis=0)))
+    v = vec[:, best] / jx[best]
+    return lam[best], v

@@ -14,6 +14,9 @@ P6  paper wall rule mass budget       -- exact leak identity
 P7  periodic conservation             -- mass, momentum + N F
 P8  north-wall worked example         -- tests/golden/north_wall.txt
 P9  memory formulas                   -- tests/golden/memory_example.txt
+P10 stored-population BGK, any tau    -- array form = loop form; linear theory of the
+                                         shear mode (9 x 9 eigenproblem); viscosity
+                                         (tau - 1/2)/3; exact steady parabola; conservation
 """
 import math
 import os
@@ -402,3 +405,84 @@ def test_lid_cavity_mass_is_not_conserved_but_fixed_row_is_held():
     r, u, v = oracle.run(rho, jx, np.zeros((ny, nx)), 200, flags, 0, (0, 0), 0)
     assert np.array_equal(u[-1], jx[-1]) and np.array_equal(r[-1], rho[-1])
     assert u[-2, nx // 2] > 0.01        # the lid drags the top fluid row along
+
+
+# ----------------------------------------------------------------- P10 BGK at any tau
+@pytest.mark.parametrize("periodic", [0, 1, 3])
+@pytest.mark.parametrize("wall", [bgk.WALL_PAPER, bgk.WALL_HALFWAY])
+def test_p10_bgk_array_form_equals_loop_form(periodic, wall):
+    rng = _rng(40 + periodic)
+    ny, nx = 9, 11
+    rho, jx, jy = _random_state(rng, ny, nx)
+    flags = (rng.random((ny, nx)) < 0.15).astype(np.uint8)
+    flags[-1, 2:6] = oracle.FIXED
+    for tau in (0.6, 1.0, 1.7):
+        a = bgk.BGK(rho, jx, jy, flags, periodic, (1e-4, -2e-5), wall, tau)
+        b = bgk.BGK(rho, jx, jy, flags, periodic, (1e-4, -2e-5), wall, tau)
+        for _ in range(15):
+            a.step()
+            b.step_arrays()
+        assert np.array_equal(a.f, b.f), tau
+
+
+@pytest.mark.parametrize("tau", [0.55, 0.8, 1.0, 1.7])
+@pytest.mark.parametrize("m", [1, 3])
+def test_p10_bgk_shear_mode_follows_linear_theory(tau, m):
+    """Section 2, Eq. lbm: a small shear wave set on the shear eigenvector of the
+    linearised one-step operator decays by its eigenvalue each step."""
+    ny, nx, A, n = 32, 4, 1e-8, 12
+    kap = 2 * np.pi * m / ny
+    lam, v = bgk.shear_mode(tau, kap)
+    y = np.arange(ny)
+    g = bgk.BGK(np.ones((ny, nx)), np.zeros((ny, nx)), np.zeros((ny, nx)), None, 3, (0.0, 0.0), 0, tau)
+    w = np.array(bgk.W)[:, None, None]
+    wave = lambda t: np.real(A * lam ** t * v[:, None, None] * np.exp(1j * kap * y)[None, :, None])
+    g.f = w + wave(0) * np.ones((1, 1, nx))
+    g.run(n, arrays=True)
+    err = np.abs(g.f - (w + wave(n))).max() / (A * abs(lam) ** n)
+    assert err < 1e-6, err
+    if tau == 1.0:      # the moments-only closed form of P3
+        assert lam.real == pytest.approx(cf.shear_wave_factor(kap), abs=1e-14)
+
+
+@pytest.mark.parametrize("tau", [0.6, 0.8, 1.3])
+def test_p10_bgk_viscosity(tau):
+    """Eq. viscosity: the shear mode decays as 1 - nu kappa^2 with nu = (tau - 1/2)/3."""
+    kap = 2 * np.pi / 4096
+    lam, _ = bgk.shear_mode(tau, kap)
+    assert (1 - lam.real) / kap ** 2 == pytest.approx((tau - 0.5) / 3, rel=1e-5)
+
+
+@pytest.mark.parametrize("tau", [0.7, 1.3])
+@pytest.mark.parametrize("wall", [bgk.WALL_PAPER, bgk.WALL_HALFWAY])
+def test_p10_bgk_steady_channel_is_exact_parabola(tau, wall):
+    """A body-force channel at steady state: the velocity profile has constant
+    second difference -F / nu, nu = (tau - 1/2)/3 (Eq. viscosity), under both wall
+    rules; the density stays 1."""
+    ny, nx, F = 12, 3, 1e-6
+    flags = np.zeros((ny, nx), np.uint8)
+    flags[0] = flags[-1] = oracle.SOLID
+    g = bgk.BGK(np.ones((ny, nx)), np.zeros((ny, nx)), np.zeros((ny, nx)), flags, 1, (F, 0.0), wall, tau)
+    nu = (tau - 0.5) / 3
+    g.run(int(45 / (nu * (np.pi / (ny - 2)) ** 2)), arrays=True)
+    rho, jx, _ = g.moments()
+    u = (jx / rho)[1:-1, 1]
+    d2 = u[2:] - 2 * u[1:-1] + u[:-2]
+    assert np.abs(d2 / (-F / nu) - 1).max() < 1e-8
+    assert np.abs(rho[1:-1] - 1).max() < 1e-11
+
+
+@pytest.mark.parametrize("tau", [0.6, 1.4])
+def test_p10_bgk_periodic_conservation(tau):
+    """Collision keeps mass and adds F to the momentum of every node (velocity-shift
+    force); streaming moves populations: over n steps mass is unchanged and the total
+    momentum grows by n N F."""
+    rng = _rng(77)
+    ny, nx, n, F = 13, 17, 30, (3e-5, -1e-5)
+    rho, jx, jy = _random_state(rng, ny, nx)
+    g = bgk.BGK(rho, jx, jy, None, 3, F, 0, tau)
+    M0, X0, Y0 = rho.sum(), jx.sum(), jy.sum()
+    r, x, y = g.run(n, arrays=True)
+    assert abs(r.sum() - M0) <= 8 * EPS * n * M0
+    assert x.sum() == pytest.approx(X0 + n * nx * ny * F[0], abs=1e-12)
+    assert y.sum() == pytest.approx(Y0 + n * nx * ny * F[1], abs=1e-12)
