@@ -20,7 +20,9 @@ The JSON line carries:
                error against the FP64 run
 
 Other workloads: --workload cavities (batched uneven cavities vs one grid per
-launch), --workload serve (continuous-batching server vs FIFO); each prints its
+launch), --workload serve (continuous-batching server vs FIFO), --workload
+compare (LBMTau1 against the stored-population BGK method on the same field:
+the paper's memory comparison measured, and the speed ratio); each prints its
 own line.
 """
 import argparse
@@ -49,7 +51,7 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=1000)
     p.add_argument("--warmup", type=int, default=100)
-    p.add_argument("--workload", default="periodic", choices=["periodic", "cavities", "serve"])
+    p.add_argument("--workload", default="periodic", choices=["periodic", "cavities", "serve", "compare"])
     p.add_argument("--n", type=int, default=8192, help="grid side of the periodic workload")
     p.add_argument("--storage", default="f32", choices=["f64", "f32", "f16s", "bf16s"])
     p.add_argument("--no-variants", action="store_true", help="skip the other storage variants")
@@ -286,6 +288,71 @@ def run_periodic(args, torch):
     return line
 
 
+def run_compare(args, torch):
+    """LBMTau1 (two fused steps per launch, and one step per launch) against the
+    stored-population BGK method (tau = 1 and tau = 0.6) on the periodic field:
+    device bytes per node and MLUPS for each, in the storage format asked for."""
+    from paper_1912_09327_amd import _capi as C
+    from paper_1912_09327_amd import inputs as I
+    from paper_1912_09327_amd.grid import Grid
+    n, st = args.n, args.storage
+    c = VALUE_BYTES[st]
+    log(f"[compare] generating the {n}x{n} periodic field (seed 0)")
+    state = I.random_periodic(n, n, seed=0)
+    lups = float(n) * n
+    rows = {}
+    vec_fused = 4 if st == "f32" else 2
+    variants = [
+        ("lbmtau1_fused", dict(populations=False), ("strip", vec_fused, 6 if st in ("f32", "f64") else 14, 0, 2)),
+        ("lbmtau1_single", dict(populations=False), ("strip", 4 if st != "f64" else 2, 6, 0, 1)),
+        ("bgk_tau1", dict(populations=True, tau=1.0), None),
+        ("bgk_tau0.6", dict(populations=True, tau=0.6), None),
+    ]
+    for name, kw, kern in variants:
+        g = Grid(n, n, prec=st, periodic=3, **kw)
+        g.set_geometry(None, *state)
+        if kern:
+            g.set_kernel(*kern)
+        cfg, kname = g.kernel()
+        log(f"[compare] {name}: {kname}")
+        wall, kms = timed_run(g, args.steps, args.warmup, torch)
+        K = cfg.get("fuse", 1) if cfg.get("kernel") == 2 else 1
+        per_node = (2 * 9 * c) if kw["populations"] else (2 * 3 * c)     # state bytes per node
+        alg = per_node * lups                                          # read + write per launch
+        rows[name] = dict(kernel=kname, mlups=round(lups * args.steps / wall / 1e6, 1),
+                          steps_per_launch=K, launch_ms=round(kms * K, 5),
+                          achieved_GBps=round(alg / (kms * K * 1e-3) / 1e9, 1),
+                          # without the residual snapshot (the paper's counts have none)
+                          device_bytes_per_node=round(C.grid_bytes(n, n, C.PRECISIONS[st],
+                                                                   g.options & ~C.OPT_SNAPSHOT) / lups, 3),
+                          state_bytes_per_node=per_node)
+        log(f"[compare] {name}: {rows[name]['mlups']:.0f} MLUPS, {rows[name]['achieved_GBps']:.0f} GB/s")
+        g.close()
+        torch.cuda.empty_cache()
+    f, s1, b = rows["lbmtau1_fused"], rows["lbmtau1_single"], rows["bgk_tau1"]
+    return {
+        "metric": METRIC,
+        "value": f["mlups"],
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": None,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if st == "f64" else "f32",
+        "data": "synthetic",
+        "config": {"workload": f"LBMTau1 vs stored-population BGK, periodic {n}x{n} random field (seed 0), "
+                               f"{st} storage", "nx": n, "ny": n, "storage": st},
+        "methods": rows,
+        "memory_ratio_bgk_over_lbmtau1": round(b["device_bytes_per_node"] / f["device_bytes_per_node"], 3),
+        "speed_ratio_lbmtau1_over_bgk": round(f["mlups"] / b["mlups"], 2),
+        "speed_ratio_single_step_over_bgk": round(s1["mlups"] / b["mlups"], 2),
+        "paper_memory_per_node_float": {"standard_AB": 84, "lbmtau1": 24, "note": "section 4, formulas"},
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -299,6 +366,8 @@ def main():
         return 1
     if args.workload == "periodic":
         line = run_periodic(args, torch)
+    elif args.workload == "compare":
+        line = run_compare(args, torch)
     elif args.workload == "cavities":
         from paper_1912_09327_amd.workloads import bench_cavities
         line = bench_cavities(args, torch, log)

@@ -85,10 +85,19 @@ enum { LBT1_PERIODIC_X = 1u, LBT1_PERIODIC_Y = 2u };
 /* lbt1_grid_desc.options bits */
 enum {
   LBT1_OPT_SNAPSHOT = 1u, /* keep a copy of the state for the residual */
-  LBT1_OPT_PLANAR = 2u    /* store rho - 1, jx, jy as three separate planes; by default
+  LBT1_OPT_PLANAR = 2u,   /* store rho - 1, jx, jy as three separate planes; by default
                              the three rows of each lattice row are adjacent in memory
                              ([ny][3][pitch]), so a row is one contiguous read and one
                              contiguous write */
+  LBT1_OPT_POPULATIONS = 4u /* the standard stored-population D2Q9 BGK method instead of
+                             LBMTau1 (section 2, Eq. lbm, with relaxation time
+                             lbt1_grid_desc.tau): two parities of nine population fields,
+                             each stored as the deviation f_q - w_q in the grid's storage
+                             format (scale[0] applies), (2 Q) c bytes per node against
+                             LBMTau1's 2 N_f c (section 4).  Same flags, walls, lid and
+                             force rules; the equilibrium velocity is (j + tau F) / rho.
+                             lbt1_step runs one kernel (set_kernel/autotune: EINVAL); the
+                             grid cannot join a batch */
 };
 
 /* lbt1_reduce what-mask bits and output slots */
@@ -119,13 +128,17 @@ typedef struct {
                             library allocates */
   size_t device_bytes;   /* size of device_buffer */
   void *stream;          /* hipStream_t to run on; NULL: a library-owned stream */
+  double tau;            /* relaxation time of LBT1_OPT_POPULATIONS grids, > 1/2 (0 means
+                            1); other grids are LBMTau1 (tau = 1): 0 or 1 only */
 } lbt1_grid_desc;
 
 /* Device bytes a grid of this shape needs: two parities of the three moment
  * fields (the paper's 2 N_f c per node, Eq. LBMTau1memory, with rows padded
  * to 64 values), one flag byte per node, one more copy of the three fields
- * with LBT1_OPT_SNAPSHOT, and a small reduction workspace.  0 on bad
- * arguments. */
+ * with LBT1_OPT_SNAPSHOT, and a small reduction workspace.  With
+ * LBT1_OPT_POPULATIONS two parities of nine population fields (2 Q c per
+ * node, Eq. lbmmemory without the separate moment arrays) replace the moment
+ * fields.  0 on bad arguments. */
 size_t lbt1_grid_bytes(int32_t nx, int32_t ny, int32_t prec, uint32_t options);
 
 /* Create a grid (no device work yet besides allocation).  *out receives the handle. */
@@ -154,6 +167,17 @@ lbt1_status lbt1_read_moments(lbt1_grid *g, double *rho, double *jx, double *jy)
  * not inside the grid.  Synchronises the grid's stream. */
 lbt1_status lbt1_read_window(lbt1_grid *g, int32_t x0, int32_t y0, int32_t w, int32_t h, double *rho, double *jx,
                              double *jy);
+
+/* LBT1_OPT_POPULATIONS grids: copy the nine populations f_q = w_q + stored
+ * deviation into a host array of 9 * ny * nx doubles, [9][ny][nx] in the
+ * direction order of section 2 (the populations after streaming, before the
+ * next collision; FIXED nodes hold the equilibrium of their moments with the
+ * force shift).  EINVAL for other grids.  Synchronises the grid's stream.
+ * For these grids lbt1_read_moments/lbt1_read_window report rho = sum f and
+ * j = sum e f of FLUID nodes (summed in FP64 on the host from the decoded
+ * populations) and the moments given to lbt1_set_geometry for SOLID and
+ * FIXED nodes. */
+lbt1_status lbt1_read_populations(lbt1_grid *g, double *f);
 
 /* FP64 diagnostics over FLUID nodes, see LBT1_REDUCE_*; out has
  * LBT1_REDUCE_SLOTS doubles, slots not asked for are left untouched except

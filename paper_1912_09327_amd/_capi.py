@@ -25,6 +25,7 @@ FLUID, SOLID, FIXED = 0, 1, 2
 PERIODIC_X, PERIODIC_Y = 1, 2
 OPT_SNAPSHOT = 1
 OPT_PLANAR = 2
+OPT_POPULATIONS = 4
 REDUCE_MASS, REDUCE_MOMENTUM, REDUCE_RESIDUAL, REDUCE_NONFINITE = 1, 2, 4, 8
 REDUCE_ALL = 15
 REDUCE_SLOTS = 6
@@ -46,7 +47,7 @@ class GridDesc(ctypes.Structure):
         ("prec", ctypes.c_int32), ("wall", ctypes.c_int32), ("options", ctypes.c_uint32),
         ("force", ctypes.c_double * 2), ("scale", ctypes.c_double * 2),
         ("device_buffer", ctypes.c_void_p), ("device_bytes", ctypes.c_size_t),
-        ("stream", ctypes.c_void_p),
+        ("stream", ctypes.c_void_p), ("tau", ctypes.c_double),
     ]
 
 
@@ -71,6 +72,7 @@ SIGNATURES = {
     "lbt1_step": (ctypes.c_int, [_vp, ctypes.c_int64]),
     "lbt1_read_moments": (ctypes.c_int, [_vp, _dp, _dp, _dp]),
     "lbt1_read_window": (ctypes.c_int, [_vp, _i32, _i32, _i32, _i32, _dp, _dp, _dp]),
+    "lbt1_read_populations": (ctypes.c_int, [_vp, _dp]),
     "lbt1_reduce": (ctypes.c_int, [_vp, ctypes.c_uint32, _dp]),
     "lbt1_sync": (ctypes.c_int, [_vp]),
     "lbt1_destroy_grid": (ctypes.c_int, [_vp]),

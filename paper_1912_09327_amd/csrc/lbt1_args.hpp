@@ -24,6 +24,31 @@ struct ReduceArgs {
   double *partials;      // 6 per block
 };
 
+// Stored-population BGK step (grids created with LBT1_OPT_POPULATIONS): nine
+// deviation fields g_q = f_q - w_q per parity.
+struct BgkArgs {
+  const void *src[9];   // fields of the current parity (pre-collision populations)
+  void *dst[9];         // fields of the next parity
+  const uint8_t *flags; // NULL: every node FLUID and both axes periodic
+  int nx, ny, pitch, rs;
+  uint32_t periodic;
+  double fx, fy;        // tau * F: the velocity-shift force of the equilibrium
+  double omega;         // 1 / tau
+  double sc, is;        // decode / encode scale of the populations
+  int tiles_x, tiles;   // 64 x 4 node tiles per tile row / in all
+  int per_xcd;          // consecutive tiles per XCD (launch: 8 * per_xcd blocks)
+};
+
+struct BgkReduceArgs {
+  const void *cur[9];
+  void *snap[3];        // moments (rho - 1, jx, jy) at the last residual call, planar
+  const uint8_t *flags;
+  int nx, ny, pitch, rs, snap_rs;
+  double sc, sc_d, sc_j, is_d, is_j;
+  uint32_t what;
+  double *partials;
+};
+
 // Descriptor of one resident grid (device copy refreshed by the host before
 // every burst).  parity0 is the grid's parity at the start of the burst;
 // the grid takes steps_left (<= burst length) steps in this burst.

@@ -6,10 +6,10 @@
 
 namespace lbt1 {
 
-enum : int { KIND_GATHER = 1, KIND_STRIP = 2 };
+enum : int { KIND_GATHER = 1, KIND_STRIP = 2, KIND_BGK = 3 };
 
 // One built step kernel.  Gather kernels take (StepArgs); strip kernels take
-// (StepArgs, StripMap).
+// (StepArgs, StripMap); population (BGK) kernels take (BgkArgs).
 struct StepKernel {
   int prec, haswall, wall, kind, vec, rows;
   const void *fn;
@@ -20,6 +20,7 @@ struct StepKernel {
 const StepKernel *step_kernels(int *count);
 const void *reduce_partial_kernel(int prec);
 const void *reduce_final_kernel();
+const void *bgk_reduce_partial_kernel(int prec);
 const void *batch_step_kernel(int prec, int vec_class, int rows);
 const void *batch_reduce_kernel(int prec);
 const void *batch_reduce_final_kernel();

@@ -1,6 +1,7 @@
 // Instantiation of the step and reduction kernels and the table the runtime
 // selects from.
 #include "lbt1_internal.hpp"
+#include "lbt1_bgk.hpp"
 #include "lbt1_fused.hpp"
 #include "lbt1_step.hpp"
 
@@ -37,6 +38,9 @@ __global__ void __launch_bounds__(64) k_reduce_final(const double *partials, int
 // kernel that spills or uses scratch memory)
 #define STRIP_ROWS_NOWALL(P, V) STRIP(P, false, 0, V, 6), STRIP(P, false, 0, V, 14)
 #define GATHER_ALL(P) GATHER(P, false, 0), GATHER(P, true, 0), GATHER(P, true, 1)
+#define BGK(P, HW, W) \
+  {P, HW, W, KIND_BGK, 0, 0, (const void *)&k_bgk_step<P, HW, W>, "k_bgk_step<" #P "," #HW "," #W ">", 1}
+#define BGK_ALL(P) BGK(P, false, 0), BGK(P, true, 0), BGK(P, true, 1)
 
 static const StepKernel kTable[] = {
     GATHER_ALL(P_F64),     GATHER_ALL(P_F32),     GATHER_ALL(P_F16S),    GATHER_ALL(P_BF16S),
@@ -48,6 +52,7 @@ static const StepKernel kTable[] = {
     FUSED_ROWS(P_F64, 2, 2),   FUSED_ROWS(P_F32, 2, 2),   FUSED_ROWS(P_F32, 4, 2),
     FUSED_ROWS(P_F16S, 2, 2),  FUSED_ROWS(P_F16S, 4, 2),  FUSED_ROWS(P_BF16S, 2, 2),
     FUSED_ROWS(P_BF16S, 4, 2),
+    BGK_ALL(P_F64), BGK_ALL(P_F32), BGK_ALL(P_F16S), BGK_ALL(P_BF16S),
 };
 
 const StepKernel *step_kernels(int *count) {
@@ -66,6 +71,16 @@ const void *reduce_partial_kernel(int prec) {
 }
 
 const void *reduce_final_kernel() { return (const void *)&k_reduce_final; }
+
+const void *bgk_reduce_partial_kernel(int prec) {
+  switch (prec) {
+    case P_F64: return (const void *)&k_bgk_reduce_partial<P_F64>;
+    case P_F32: return (const void *)&k_bgk_reduce_partial<P_F32>;
+    case P_F16S: return (const void *)&k_bgk_reduce_partial<P_F16S>;
+    case P_BF16S: return (const void *)&k_bgk_reduce_partial<P_BF16S>;
+  }
+  return nullptr;
+}
 
 // Batched kernels (always wall-aware): [precision][vec class 0..2 = vec 1, 2, 4]
 // for strips of 14 rows (tall) and 6 rows (short: half the serial latency of a

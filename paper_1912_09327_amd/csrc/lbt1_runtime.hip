@@ -64,27 +64,38 @@ Layout layout_of(int nx, int ny, int prec, uint32_t options) {
   const size_t c = value_bytes(prec);
   L.pitch = (int)round_up((size_t)nx, 64);
   L.interleaved = !(options & LBT1_OPT_PLANAR);
+  const bool pop = options & LBT1_OPT_POPULATIONS;
+  const int nf = pop ? 9 : 3;
+  L.nfield = nf;
+  const size_t plane = round_up((size_t)L.pitch * ny * c, 256);
   if (L.interleaved) {
-    // [ny][3][pitch]: a wavefront reading (writing) one lattice row touches one
+    // [ny][nf][pitch]: a wavefront reading (writing) one lattice row touches one
     // contiguous stretch of the parity block
-    L.rs = 3 * L.pitch;
-    for (int q = 0; q < 3; ++q) L.field_off[q] = (size_t)q * L.pitch * c;
-    L.state = round_up((size_t)3 * L.pitch * ny * c, 256);
+    L.rs = nf * L.pitch;
+    for (int q = 0; q < nf; ++q) L.field_off[q] = (size_t)q * L.pitch * c;
+    L.state = round_up((size_t)nf * L.pitch * ny * c, 256);
   } else {
-    // [3][ny][pitch]: three separate planes
-    const size_t plane = round_up((size_t)L.pitch * ny * c, 256);
+    // [nf][ny][pitch]: separate planes
     L.rs = L.pitch;
-    for (int q = 0; q < 3; ++q) L.field_off[q] = (size_t)q * plane;
-    L.state = 3 * plane;
+    for (int q = 0; q < nf; ++q) L.field_off[q] = (size_t)q * plane;
+    L.state = nf * plane;
   }
   L.flags_off = 2 * L.state;
   L.flags_bytes = round_up((size_t)L.pitch * ny, 256);
   size_t off = L.flags_off + L.flags_bytes;
+  L.snap_off = 0;
+  L.snap_rs = L.rs;
+  for (int q = 0; q < 3; ++q) L.snap_field_off[q] = L.field_off[q];
   if (options & LBT1_OPT_SNAPSHOT) {
     L.snap_off = off;
-    off += L.state;
-  } else {
-    L.snap_off = 0;
+    if (pop) {
+      // the residual compares moments: three planes of rho - 1, jx, jy
+      L.snap_rs = L.pitch;
+      for (int q = 0; q < 3; ++q) L.snap_field_off[q] = (size_t)q * plane;
+      off += 3 * plane;
+    } else {
+      off += L.state;
+    }
   }
   L.nparts = kReduceBlocks;
   L.part_off = off;
@@ -285,6 +296,20 @@ lbt1_kernel_config heuristic_config(int prec, bool haswall, int wall, int nx, in
 
 // Resolve a configuration into a kernel and launch shape for grid g.
 lbt1_status bind_config(lbt1_grid *g, const lbt1_kernel_config &want, int cus) {
+  if (g->pop) {
+    // one kernel: a thread per node (the gather launch shape)
+    const StepKernel *k = find_kernel(g->prec, g->haswall, g->wall, KIND_BGK, 0, 0, 1);
+    if (!k) return fail(LBT1_EINVAL, "no built population kernel at this precision");
+    g->kern = g->kern1 = k;
+    g->cfg = lbt1_kernel_config{};
+    g->cfg.kernel = LBT1_KERNEL_GATHER;
+    g->cfg.fuse = 1;
+    const int tiles = ((g->nx + 63) / 64) * ((g->ny + 3) / 4);
+    g->block = dim3(256, 1, 1);
+    g->grid = dim3((tiles + 7) / 8 * 8, 1, 1);
+    g->graph_valid = false;
+    return LBT1_OK;
+  }
   lbt1_kernel_config c = want;
   if (c.kernel == LBT1_KERNEL_AUTO) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -364,9 +389,37 @@ StepArgs step_args(const lbt1_grid *g, int src_parity) {
   return a;
 }
 
+BgkArgs bgk_args(const lbt1_grid *g, int src_parity) {
+  BgkArgs a{};
+  for (int q = 0; q < 9; ++q) {
+    a.src[q] = g->plane[src_parity][q];
+    a.dst[q] = g->plane[1 - src_parity][q];
+  }
+  a.flags = g->haswall ? g->flags : nullptr;
+  a.nx = g->nx;
+  a.ny = g->ny;
+  a.pitch = g->L.pitch;
+  a.rs = g->L.rs;
+  a.periodic = g->periodic;
+  a.fx = g->tau * g->F[0];
+  a.fy = g->tau * g->F[1];
+  a.omega = 1.0 / g->tau;
+  a.sc = g->sc[0];
+  a.is = 1.0 / g->sc[0];
+  a.tiles_x = (g->nx + 63) / 64;
+  a.tiles = a.tiles_x * ((g->ny + 3) / 4);
+  a.per_xcd = (a.tiles + 7) / 8;
+  return a;
+}
+
 // One launch of kernel k (g->kern, or its single-step companion g->kern1,
 // which has the same launch shape) reading parity src_parity.
 hipError_t launch_step(lbt1_grid *g, const StepKernel *k, int src_parity, hipStream_t s) {
+  if (k->kind == KIND_BGK) {
+    BgkArgs b = bgk_args(g, src_parity);
+    void *args[] = {&b};
+    return hipLaunchKernel(k->fn, g->grid, g->block, args, 0, s);
+  }
   StepArgs a = step_args(g, src_parity);
   if (k->kind == KIND_GATHER) {
     void *args[] = {&a};
@@ -389,17 +442,19 @@ static lbt1_status build_burst(lbt1_grid *g, int p) {
   hipGraphNode_t prev = nullptr;
   const int launches = kBurst / g->kern->steps;
   std::vector<StepArgs> argv(launches);
+  std::vector<BgkArgs> bargv(g->pop ? launches : 0);
   StripMap m = g->map;
   for (int s = 0; s < launches; ++s) {
     argv[s] = step_args(g, (p + s) & 1);
-    void *args_gather[] = {&argv[s]};
+    if (g->pop) bargv[s] = bgk_args(g, (p + s) & 1);
+    void *args_gather[] = {g->pop ? (void *)&bargv[s] : (void *)&argv[s]};
     void *args_strip[] = {&argv[s], &m};
     hipKernelNodeParams kp{};
     kp.func = const_cast<void *>(g->kern->fn);
     kp.gridDim = g->grid;
     kp.blockDim = g->block;
     kp.sharedMemBytes = 0;
-    kp.kernelParams = g->kern->kind == KIND_GATHER ? args_gather : args_strip;
+    kp.kernelParams = g->kern->kind == KIND_STRIP ? args_strip : args_gather;
     kp.extra = nullptr;
     hipGraphNode_t node;
     e = hipGraphAddKernelNode(&node, graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
@@ -458,7 +513,39 @@ lbt1_status enqueue_steps(lbt1_grid *g, int64_t n, hipStream_t s, bool use_graph
   return LBT1_OK;
 }
 
+static lbt1_status enqueue_reduce_pop(lbt1_grid *g, uint32_t what, hipStream_t s) {
+  BgkReduceArgs a{};
+  for (int q = 0; q < 9; ++q) a.cur[q] = g->plane[g->parity][q];
+  for (int q = 0; q < 3; ++q) a.snap[q] = g->snap[q];
+  a.flags = g->haswall ? g->flags : nullptr;
+  a.nx = g->nx;
+  a.ny = g->ny;
+  a.pitch = g->L.pitch;
+  a.rs = g->L.rs;
+  a.snap_rs = g->L.snap_rs;
+  a.sc = g->sc[0];
+  a.sc_d = g->sc[0];
+  a.sc_j = g->sc[1];
+  a.is_d = 1.0 / g->sc[0];
+  a.is_j = 1.0 / g->sc[1];
+  a.what = what;
+  a.partials = g->partials;
+  const long n = (long)g->nx * g->ny;
+  const int blocks = (int)std::min<long>(g->L.nparts, std::max<long>(1, (n + 1023) / 1024));
+  void *args[] = {&a};
+  hipError_t e = hipLaunchKernel(bgk_reduce_partial_kernel(g->prec), dim3(blocks), dim3(256), args, 0, s);
+  if (e != hipSuccess) return hip_fail(e, "reduce launch");
+  const double *parts = g->partials;
+  int np = blocks;
+  double *out = g->red_out;
+  void *args2[] = {&parts, &np, &out};
+  e = hipLaunchKernel(reduce_final_kernel(), dim3(1), dim3(64), args2, 0, s);
+  if (e != hipSuccess) return hip_fail(e, "reduce launch");
+  return LBT1_OK;
+}
+
 lbt1_status enqueue_reduce(lbt1_grid *g, uint32_t what, hipStream_t s) {
+  if (g->pop) return enqueue_reduce_pop(g, what, s);
   ReduceArgs a{};
   for (int q = 0; q < 3; ++q) {
     a.cur[q] = g->plane[g->parity][q];
@@ -487,6 +574,107 @@ lbt1_status enqueue_reduce(lbt1_grid *g, uint32_t what, hipStream_t s) {
   return LBT1_OK;
 }
 
+// D2Q9 tables of section 2 for the host-side initialisation of population grids.
+static const int kHostEx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+static const int kHostEy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+static const double kHostW[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+
+// Populations of a stored-population grid at t = 0: the equilibrium
+// (Eq. maxwellboltzmann, FP64) of each FLUID node's moments, that of the
+// moments with the force shift tau F for FIXED nodes (what they send every
+// step), w_q for SOLID nodes; stored as deviations f_q - w_q.
+static lbt1_status set_geometry_pop(lbt1_grid *g, const uint8_t *flags, const double *rho, const double *jx,
+                                    const double *jy) {
+  const int nx = g->nx, ny = g->ny, pitch = g->L.pitch;
+  const size_t c = value_bytes(g->prec);
+  const size_t plane = (size_t)pitch * ny;
+  std::vector<char> stage, sstage;
+  std::vector<uint8_t> fstage;
+  std::vector<double> rows;
+  try {
+    stage.assign(g->L.state, 0);
+    fstage.assign(plane, LBT1_SOLID);
+    if (g->snap[0]) sstage.assign(g->L.snap_field_off[2] + plane * c, 0);
+    rows.assign((size_t)12 * nx, 0.0);
+    g->given_idx.clear();
+    g->given_val.clear();
+  } catch (...) {
+    return fail(LBT1_ENOMEM, "host staging");
+  }
+  double *mom = rows.data() + (size_t)9 * nx;  // rho - 1, jx, jy of one row
+  for (int y = 0; y < ny; ++y) {
+    for (int x = 0; x < nx; ++x) {
+      const size_t i = (size_t)y * nx + x;
+      const uint8_t fl = flags ? flags[i] : LBT1_FLUID;
+      const double r = rho ? rho[i] : 1.0, a = jx ? jx[i] : 0.0, b = jy ? jy[i] : 0.0;
+      if (fl != LBT1_FLUID) {
+        g->given_idx.push_back(i);
+        g->given_val.insert(g->given_val.end(), {r, a, b});
+      }
+      mom[x] = r - 1.0;
+      mom[nx + x] = a;
+      mom[2 * nx + x] = b;
+      if (fl == LBT1_SOLID) {
+        for (int q = 0; q < 9; ++q) rows[(size_t)q * nx + x] = 0.0;
+        continue;
+      }
+      const double shift = fl == LBT1_FIXED ? g->tau : 0.0;
+      const double ux = (a + shift * g->F[0]) / r, uy = (b + shift * g->F[1]) / r;
+      const double usq = ux * ux + uy * uy;
+      for (int q = 0; q < 9; ++q) {
+        const double eu = kHostEx[q] * ux + kHostEy[q] * uy;
+        rows[(size_t)q * nx + x] = kHostW[q] * r * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * usq) - kHostW[q];
+      }
+    }
+    for (int q = 0; q < 9; ++q)
+      encode_values(g->prec, rows.data() + (size_t)q * nx, nx, 1.0 / g->sc[0],
+                    stage.data() + g->L.field_off[q] + (size_t)y * g->L.rs * c);
+    if (g->snap[0])
+      for (int q = 0; q < 3; ++q)
+        encode_values(g->prec, mom + (size_t)q * nx, nx, 1.0 / g->sc[q == 0 ? 0 : 1],
+                      sstage.data() + g->L.snap_field_off[q] + (size_t)y * g->L.snap_rs * c);
+    for (int x = 0; x < nx; ++x) fstage[(size_t)y * pitch + x] = flags ? flags[(size_t)y * nx + x] : LBT1_FLUID;
+  }
+  hipError_t e;
+  if ((e = hipSetDevice(g->device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
+  if ((e = hipStreamSynchronize(g->stream)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  for (int p = 0; p < 2; ++p)
+    if ((e = hipMemcpy(g->base + (size_t)p * g->L.state, stage.data(), g->L.state, hipMemcpyHostToDevice)) != hipSuccess)
+      return hip_fail(e, "hipMemcpy H2D");
+  if (g->snap[0] && (e = hipMemcpy(g->base + g->L.snap_off, sstage.data(), sstage.size(), hipMemcpyHostToDevice)) != hipSuccess)
+    return hip_fail(e, "hipMemcpy H2D");
+  if ((e = hipMemcpy(g->flags, fstage.data(), plane, hipMemcpyHostToDevice)) != hipSuccess)
+    return hip_fail(e, "hipMemcpy H2D");
+  return LBT1_OK;
+}
+
+// Decode the populations of rows y0..y0+h-1, columns x0..x0+w-1 of the current
+// parity into f[q][h][w] (deviations plus w_q).
+static lbt1_status read_pop_window(lbt1_grid *g, int x0, int y0, int w, int h, std::vector<double> &f) {
+  const size_t c = value_bytes(g->prec);
+  const size_t n = (size_t)w * h;
+  std::vector<char> stage;
+  try {
+    stage.resize(n * c);
+    f.resize(9 * n);
+  } catch (...) {
+    return fail(LBT1_ENOMEM, "host staging");
+  }
+  hipError_t e;
+  if ((e = hipSetDevice(g->device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
+  if ((e = hipStreamSynchronize(g->stream)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  for (int q = 0; q < 9; ++q) {
+    const char *src = (const char *)g->plane[g->parity][q] + ((size_t)y0 * g->L.rs + x0) * c;
+    if ((e = hipMemcpy2D(stage.data(), (size_t)w * c, src, (size_t)g->L.rs * c, (size_t)w * c, h,
+                         hipMemcpyDeviceToHost)) != hipSuccess)
+      return hip_fail(e, "hipMemcpy2D D2H");
+    double *dst = f.data() + (size_t)q * n;
+    decode_values(g->prec, stage.data(), n, g->sc[0], dst);
+    for (size_t i = 0; i < n; ++i) dst[i] += kHostW[q];
+  }
+  return LBT1_OK;
+}
+
 }  // namespace lbt1
 
 using namespace lbt1;
@@ -509,7 +697,12 @@ lbt1_status lbt1_create_grid(const lbt1_grid_desc *d, lbt1_grid **out) {
   if (!valid_prec(d->prec)) return fail(LBT1_EINVAL, "unknown precision %d", d->prec);
   if (d->wall != LBT1_WALL_PAPER && d->wall != LBT1_WALL_HALFWAY) return fail(LBT1_EINVAL, "unknown wall rule %d", d->wall);
   if (d->periodic & ~3u) return fail(LBT1_EINVAL, "periodic mask %u", d->periodic);
-  if (d->options & ~(uint32_t)(LBT1_OPT_SNAPSHOT | LBT1_OPT_PLANAR)) return fail(LBT1_EINVAL, "unknown options %u", d->options);
+  if (d->options & ~(uint32_t)(LBT1_OPT_SNAPSHOT | LBT1_OPT_PLANAR | LBT1_OPT_POPULATIONS))
+    return fail(LBT1_EINVAL, "unknown options %u", d->options);
+  const bool pop = d->options & LBT1_OPT_POPULATIONS;
+  const double tau = d->tau == 0.0 ? 1.0 : d->tau;
+  if (pop && !(tau > 0.5 && std::isfinite(tau))) return fail(LBT1_EINVAL, "tau = %g: must be finite and > 1/2", d->tau);
+  if (!pop && tau != 1.0) return fail(LBT1_EINVAL, "tau = %g: LBMTau1 grids have tau = 1 (0 or 1)", d->tau);
   if (!std::isfinite(d->force[0]) || !std::isfinite(d->force[1])) return fail(LBT1_EINVAL, "force must be finite");
   if (!pow2_or_zero(d->scale[0]) || !pow2_or_zero(d->scale[1]))
     return fail(LBT1_EINVAL, "scales must be 0 or positive powers of two");
@@ -526,6 +719,8 @@ lbt1_status lbt1_create_grid(const lbt1_grid_desc *d, lbt1_grid **out) {
   g->prec = d->prec;
   g->wall = d->wall;
   g->options = d->options;
+  g->pop = pop;
+  g->tau = tau;
   g->F[0] = d->force[0];
   g->F[1] = d->force[1];
   const bool scaled = d->prec == LBT1_F16S || d->prec == LBT1_BF16S;
@@ -565,10 +760,10 @@ lbt1_status lbt1_create_grid(const lbt1_grid_desc *d, lbt1_grid **out) {
     g->own_stream = true;
   }
   for (int p = 0; p < 2; ++p)
-    for (int q = 0; q < 3; ++q) g->plane[p][q] = g->base + (size_t)p * g->L.state + g->L.field_off[q];
+    for (int q = 0; q < g->L.nfield; ++q) g->plane[p][q] = g->base + (size_t)p * g->L.state + g->L.field_off[q];
   g->flags = (uint8_t *)(g->base + g->L.flags_off);
   for (int q = 0; q < 3; ++q)
-    g->snap[q] = (d->options & LBT1_OPT_SNAPSHOT) ? g->base + g->L.snap_off + g->L.field_off[q] : nullptr;
+    g->snap[q] = (d->options & LBT1_OPT_SNAPSHOT) ? g->base + g->L.snap_off + g->L.snap_field_off[q] : nullptr;
   g->partials = (double *)(g->base + g->L.part_off);
   g->red_out = (double *)(g->base + g->L.out_off);
   if ((e = hipHostMalloc((void **)&g->red_host, 8 * sizeof(double), hipHostMallocDefault)) != hipSuccess) {
@@ -610,6 +805,17 @@ lbt1_status lbt1_set_geometry(lbt1_grid *g, const uint8_t *flags, const double *
   for (size_t i = 0; jy && i < n; ++i)
     if (!std::isfinite(jy[i])) return fail(LBT1_EINVAL, "jy[%zu] is not finite", i);
 
+  if (g->pop) {
+    lbt1_status st = set_geometry_pop(g, flags, rho, jx, jy);
+    if (st) return st;
+    g->haswall = any_nonfluid || g->periodic != 3u;
+    g->fluid = fluid;
+    g->parity = 0;
+    g->steps = 0;
+    g->geometry = true;
+    drop_bursts(g);
+    return bind_config(g, lbt1_kernel_config{}, g->cus);
+  }
   // Host staging in storage format with padded rows.
   const size_t c = value_bytes(g->prec);
   const size_t plane_vals = (size_t)pitch * ny;
@@ -683,8 +889,30 @@ lbt1_status lbt1_read_window(lbt1_grid *g, int32_t x0, int32_t y0, int32_t w, in
   if (!g->geometry) return fail(LBT1_ESTATE, "no geometry set");
   if (w <= 0 || h <= 0 || x0 < 0 || y0 < 0 || (int64_t)x0 + w > g->nx || (int64_t)y0 + h > g->ny)
     return fail(LBT1_EINVAL, "window (%d, %d) + %d x %d is not inside the %d x %d grid", x0, y0, w, h, g->nx, g->ny);
-  const size_t c = value_bytes(g->prec);
   const size_t n = (size_t)w * h;
+  if (g->pop) {
+    std::vector<double> f;
+    lbt1_status st = read_pop_window(g, x0, y0, w, h, f);
+    if (st) return st;
+    for (size_t i = 0; i < n; ++i) {
+      double v[9];
+      for (int q = 0; q < 9; ++q) v[q] = f[(size_t)q * n + i] - kHostW[q];
+      const double d = (((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]))) + v[8];
+      if (rho) rho[i] = 1.0 + d;
+      if (jx) jx[i] = ((v[1] - v[3]) + (v[5] - v[6])) + (v[8] - v[7]);
+      if (jy) jy[i] = ((v[2] - v[4]) + (v[5] - v[7])) + (v[6] - v[8]);
+    }
+    for (size_t k = 0; k < g->given_idx.size(); ++k) {
+      const int gy = (int)(g->given_idx[k] / g->nx), gx = (int)(g->given_idx[k] % g->nx);
+      if (gx < x0 || gx >= x0 + w || gy < y0 || gy >= y0 + h) continue;
+      const size_t i = (size_t)(gy - y0) * w + (gx - x0);
+      if (rho) rho[i] = g->given_val[3 * k];
+      if (jx) jx[i] = g->given_val[3 * k + 1];
+      if (jy) jy[i] = g->given_val[3 * k + 2];
+    }
+    return LBT1_OK;
+  }
+  const size_t c = value_bytes(g->prec);
   std::vector<char> stage;
   try {
     stage.resize(n * c);
@@ -714,6 +942,18 @@ lbt1_status lbt1_read_moments(lbt1_grid *g, double *rho, double *jx, double *jy)
     return fail(LBT1_EINVAL, "null grid");
   }
   return lbt1_read_window(g, 0, 0, g->nx, g->ny, rho, jx, jy);
+}
+
+lbt1_status lbt1_read_populations(lbt1_grid *g, double *f) {
+  clear_error();
+  if (!g || !f) return fail(LBT1_EINVAL, "null argument");
+  if (!g->pop) return fail(LBT1_EINVAL, "not a population grid (LBT1_OPT_POPULATIONS)");
+  if (!g->geometry) return fail(LBT1_ESTATE, "no geometry set");
+  std::vector<double> v;
+  lbt1_status st = read_pop_window(g, 0, 0, g->nx, g->ny, v);
+  if (st) return st;
+  std::memcpy(f, v.data(), v.size() * sizeof(double));
+  return LBT1_OK;
 }
 
 lbt1_status lbt1_reduce(lbt1_grid *g, uint32_t what, double *out) {
@@ -759,6 +999,7 @@ lbt1_status lbt1_destroy_grid(lbt1_grid *g) {
 lbt1_status lbt1_set_kernel(lbt1_grid *g, const lbt1_kernel_config *cfg) {
   clear_error();
   if (!g || !cfg) return fail(LBT1_EINVAL, "null argument");
+  if (g->pop) return fail(LBT1_EINVAL, "population grids have a single step kernel");
   if (!g->geometry) {
     g->cfg = *cfg;
     g->user_cfg = cfg->kernel != LBT1_KERNEL_AUTO;
@@ -797,6 +1038,7 @@ lbt1_status lbt1_autotune(lbt1_grid *g, int32_t steps, int32_t reps, lbt1_kernel
   if (!g->geometry) return fail(LBT1_ESTATE, "no geometry set");
   if (g->batch) return fail(LBT1_ESTATE, "grid is resident in a batch");
   if (steps < 2 || reps < 1) return fail(LBT1_EINVAL, "steps >= 2 and reps >= 1 required");
+  if (g->pop) return fail(LBT1_EINVAL, "population grids have a single step kernel");
   hipError_t e;
   if ((e = hipSetDevice(g->device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
   if ((e = hipStreamSynchronize(g->stream)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <string>
+#include <vector>
 
 #include "../../include/lbt1.h"
 #include "lbt1_internal.hpp"
@@ -14,12 +15,15 @@ constexpr int kReduceBlocks = 1024;  // most partial rows a reduction writes
 
 struct Layout {
   int pitch;          // values per row of one field (nx rounded up to 64)
-  int rs;             // moment row stride in values: pitch (planar) or 3 * pitch
-  bool interleaved;   // the three moment rows of a lattice row are adjacent
-  size_t field_off[3];  // byte offset of field q inside a parity block
-  size_t state;       // bytes of one parity block (three fields, 256-byte multiple)
+  int nfield;         // fields per parity: 3 moments, or 9 populations
+  int rs;             // field row stride in values: pitch (planar) or nfield * pitch
+  bool interleaved;   // the field rows of a lattice row are adjacent
+  size_t field_off[9];  // byte offset of field q inside a parity block
+  size_t state;       // bytes of one parity block (all fields, 256-byte multiple)
   size_t flags_off, flags_bytes;
   size_t snap_off;    // 0 without LBT1_OPT_SNAPSHOT
+  int snap_rs;        // row stride of the snapshot's three moment fields
+  size_t snap_field_off[3];
   int nparts;
   size_t part_off, out_off, trash_off;
   size_t total;
@@ -39,6 +43,8 @@ struct lbt1_grid {
   uint32_t periodic = 0;
   int prec = 0, wall = 0;
   uint32_t options = 0;
+  bool pop = false;       // LBT1_OPT_POPULATIONS: stored-population BGK
+  double tau = 1.0;
   double F[2] = {0, 0};
   double sc[2] = {1, 1};  // decode scales of d and j
   lbt1::Layout L{};
@@ -46,7 +52,7 @@ struct lbt1_grid {
   bool own_stream = false;
   char *base = nullptr;
   bool own_mem = false;
-  void *plane[2][3] = {};
+  void *plane[2][9] = {};
   uint8_t *flags = nullptr;
   void *snap[3] = {};
   double *partials = nullptr;
@@ -57,6 +63,10 @@ struct lbt1_grid {
   bool geometry = false;
   bool haswall = false;
   int64_t fluid = 0;
+  // population grids: moments given to set_geometry for SOLID and FIXED nodes
+  // (reported by the readout), node index and (rho, jx, jy)
+  std::vector<size_t> given_idx;
+  std::vector<double> given_val;
   // step kernel
   lbt1_kernel_config cfg{};
   bool user_cfg = false;

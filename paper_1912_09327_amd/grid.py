@@ -34,17 +34,24 @@ def _dptr(a):
 
 
 class Grid:
-    """One ``nx`` x ``ny`` lattice.  Arrays are numpy ``[ny, nx]`` (x fastest)."""
+    """One ``nx`` x ``ny`` lattice.  Arrays are numpy ``[ny, nx]`` (x fastest).
+
+    ``populations=True`` makes a stored-population BGK grid with relaxation time
+    ``tau`` (the standard method, for comparison and tau != 1); by default the
+    grid is LBMTau1."""
 
     def __init__(self, nx, ny, prec="f32", wall="paper", periodic=0, force=(0.0, 0.0),
-                 scale=(0.0, 0.0), snapshot=True, stream=None, torch_memory=True, planar=False):
+                 scale=(0.0, 0.0), snapshot=True, stream=None, torch_memory=True, planar=False,
+                 populations=False, tau=1.0):
         import torch
         self.nx, self.ny = int(nx), int(ny)
         self.prec = _prec(prec)
         self.wall = _wall(wall)
         self.periodic = int(periodic)
         self.force = (float(force[0]), float(force[1]))
-        self.options = (C.OPT_SNAPSHOT if snapshot else 0) | (C.OPT_PLANAR if planar else 0)
+        self.options = ((C.OPT_SNAPSHOT if snapshot else 0) | (C.OPT_PLANAR if planar else 0)
+                        | (C.OPT_POPULATIONS if populations else 0))
+        self.tau = float(tau)
         self.stream = stream if stream is not None else default_stream()
         nbytes = C.grid_bytes(self.nx, self.ny, self.prec, self.options)
         if nbytes == 0:
@@ -55,6 +62,7 @@ class Grid:
         d.prec, d.wall, d.options = self.prec, self.wall, self.options
         d.force[0], d.force[1] = self.force
         d.scale[0], d.scale[1] = float(scale[0]), float(scale[1])
+        d.tau = self.tau
         self._buf = None
         if torch_memory:
             self._buf = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
@@ -86,6 +94,12 @@ class Grid:
         rho, jx, jy = np.empty(shape), np.empty(shape), np.empty(shape)
         C.check(C.lib.lbt1_read_moments(self.handle, _dptr(rho), _dptr(jx), _dptr(jy)))
         return rho, jx, jy
+
+    def read_populations(self):
+        """The nine populations f_q, [9, ny, nx] (population grids only)."""
+        f = np.empty((9, self.ny, self.nx))
+        C.check(C.lib.lbt1_read_populations(self.handle, _dptr(f)))
+        return f
 
     def read_window(self, x0, y0, w, h):
         """(rho, jx, jy) of the window x0 <= x < x0+w, y0 <= y < y0+h, each [h, w]."""

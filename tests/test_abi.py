@@ -44,6 +44,38 @@ def test_grid_bytes_is_two_parities_of_three_planes_plus_flags():
     assert 6 * 4 * 1024 * 1000 <= C.grid_bytes(1000, 1000, C.F32, 0) < 6 * 4 * 1024 * 1000 + 1_200_000
 
 
+def test_grid_bytes_of_population_grids():
+    """Eq. lbmmemory: a stored-population grid keeps two parities of Q = 9 fields
+    (18 c bytes per node of state against LBMTau1's 6 c); its snapshot holds the
+    three moment fields."""
+    from paper_1912_09327_amd import _capi as C
+    P = C.OPT_POPULATIONS
+    for prec, c in ((C.F64, 8), (C.F32, 4), (C.F16S, 2)):
+        for nx, ny in ((64, 32), (1000, 1000), (37, 5)):
+            pitch = (nx + 63) // 64 * 64
+            flags = -(-pitch * ny // 256) * 256
+            plane = -(-pitch * ny * c // 256) * 256
+            for opt, state in ((P, -(-9 * pitch * ny * c // 256) * 256), (P | C.OPT_PLANAR, 9 * plane)):
+                base = C.grid_bytes(nx, ny, prec, opt)
+                assert 0 <= base - (2 * state + flags) <= 64 * 1024
+                assert C.grid_bytes(nx, ny, prec, opt | C.OPT_SNAPSHOT) == base + 3 * plane
+    # the paper's 1000 x 1000 float cavity: 18 c = 72 bytes per node of populations
+    # (its 84 counts three more moment arrays) against 24 for LBMTau1
+    ratio = C.grid_bytes(1000, 1000, C.F32, P) / C.grid_bytes(1000, 1000, C.F32, 0)
+    assert 2.9 < ratio < 3.0
+
+
+def test_tau_is_checked():
+    from paper_1912_09327_amd import _capi as C
+    d = C.GridDesc()
+    d.nx, d.ny, d.prec, d.tau = 16, 16, C.F32, 0.8          # tau != 1 needs populations
+    h = ctypes.c_void_p()
+    assert C.lib.lbt1_create_grid(ctypes.byref(d), ctypes.byref(h)) == C.EINVAL
+    assert b"tau" in C.lib.lbt1_last_error()
+    d.options, d.tau = C.OPT_POPULATIONS, 0.5               # tau must exceed 1/2
+    assert C.lib.lbt1_create_grid(ctypes.byref(d), ctypes.byref(h)) == C.EINVAL
+
+
 def test_bad_arguments_are_rejected_before_any_device_work():
     from paper_1912_09327_amd import _capi as C
     assert C.grid_bytes(2, 10, C.F32) == 0
