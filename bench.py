@@ -22,8 +22,10 @@ The JSON line carries:
 Other workloads: --workload cavities (batched uneven cavities vs one grid per
 launch), --workload serve (continuous-batching server vs FIFO), --workload
 compare (LBMTau1 against the stored-population BGK method on the same field:
-the paper's memory comparison measured, and the speed ratio); each prints its
-own line.
+the paper's memory comparison measured, and the speed ratio), --workload
+stability (largest stable Reynolds number of the lid-driven cavity against
+grid size at tau = 1, 0.55, 0.7 and 1.5, with the power-law fits); each
+prints its own line.
 """
 import argparse
 import hashlib
@@ -51,7 +53,8 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=1000)
     p.add_argument("--warmup", type=int, default=100)
-    p.add_argument("--workload", default="periodic", choices=["periodic", "cavities", "serve", "compare"])
+    p.add_argument("--workload", default="periodic",
+                   choices=["periodic", "cavities", "serve", "compare", "stability"])
     p.add_argument("--n", type=int, default=8192, help="grid side of the periodic workload")
     p.add_argument("--storage", default="f32", choices=["f64", "f32", "f16s", "bf16s"])
     p.add_argument("--no-variants", action="store_true", help="skip the other storage variants")
@@ -353,6 +356,64 @@ def run_compare(args, torch):
     }
 
 
+def run_stability(args, torch):
+    """Re_max(L) of the lid-driven cavity: LBMTau1 at tau = 1 (every lid speed of a
+    size as one batch), the stored-population BGK method at tau = 0.55, 0.7, 1.5
+    (and 1 on the smaller sizes, as a cross-check); power-law fits beside the
+    paper's."""
+    from paper_1912_09327_amd import stability as S
+    Ls = [50, 100, 200, 400, 700, 1000]
+    speeds = S.lid_speeds(0.1, 1.6, 1.05)
+    paper = {1.0: (12.0, 0.8), 1.5: (3.7, 0.89), 0.7: (19.0, 0.87), 0.55: (43.0, 0.93)}
+    out = {}
+    lups = 0.0
+    t0 = time.perf_counter()
+    runs = [("lbmtau1", 1.0)] + [("bgk", t) for t in (0.55, 0.7, 1.5)] + [("bgk", 1.0)]
+    for method, tau in runs:
+        rows = []
+        for L in Ls:
+            if method == "bgk" and tau == 1.0 and L > 200:
+                continue
+            if method == "lbmtau1":
+                res = S.scan_batched(L, speeds, log=log)
+            else:
+                res = S.scan_populations(L, tau, speeds)
+            lups += sum(((L - 2) * (L - 1)) * n for _, _, n in res)
+            re = S.re_max_from_scan(L, tau, [(u, bad) for u, bad, _ in res])
+            first_bad = next((u for u, bad, _ in res if bad), None)
+            rows.append(dict(L=L, re_max=None if re is None else round(re, 1),
+                             u0_max=None if re is None else round(re * S.viscosity(tau) / L, 4),
+                             first_unstable_u0=None if first_bad is None else round(first_bad, 4),
+                             paper_fit=round(paper[tau][0] * L ** paper[tau][1], 1)))
+            log(f"[stability] {method} tau={tau} L={L}: Re_max {rows[-1]['re_max']} "
+                f"(paper fit {rows[-1]['paper_fit']})")
+        ok = [r for r in rows if r["re_max"]]
+        fit = S.fit_power([r["L"] for r in ok], [r["re_max"] for r in ok]) if len(ok) >= 2 else (None, None)
+        out[f"{method}_tau{tau}"] = dict(rows=rows, fit_a=fit[0] and round(fit[0], 3),
+                                         fit_b=fit[1] and round(fit[1], 4), paper_a=paper[tau][0],
+                                         paper_b=paper[tau][1])
+    wall = time.perf_counter() - t0
+    return {
+        "metric": METRIC,
+        "value": round(lups / wall / 1e6, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": None,
+        "warmup": 0,
+        "ms_per_step": None,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "lid-driven cavity Re_max(L) sweep, L in 50..1000, lid speeds 0.1 * 1.05^k up to 1.6, "
+                               "unstable = non-finite moments within max(1000, 4 L / u0) steps (at most 40000), "
+                               "FP32 storage", "sizes": Ls},
+        "seconds": round(wall, 2),
+        "sweeps": out,
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -366,6 +427,8 @@ def main():
         return 1
     if args.workload == "periodic":
         line = run_periodic(args, torch)
+    elif args.workload == "stability":
+        line = run_stability(args, torch)
     elif args.workload == "compare":
         line = run_compare(args, torch)
     elif args.workload == "cavities":

@@ -159,3 +159,17 @@ def test_bgk_refusals():
         b.close()
         g.close()
         h.close()
+
+
+def test_stability_scan_detects_blow_up():
+    """The Re_max sweep's two runners agree at tau = 1 and flag a lid far beyond the
+    stable range as unstable (non-finite moments) while a slow lid runs its horizon."""
+    from paper_1912_09327_amd import stability as S
+    speeds = [0.1, 0.6, 4.0]
+    a = S.scan_batched(50, speeds)
+    b = S.scan_populations(50, 1.0, speeds, stop_at_first=False)
+    assert [bad for _, bad, _ in a] == [bad for _, bad, _ in b]
+    assert not a[0][1] and a[0][2] == S.horizon(50, 0.1)
+    assert a[-1][1] and b[-1][1]
+    c = S.scan_populations(50, 0.7, speeds)
+    assert not c[0][1] and c[-1][1]
