@@ -7,7 +7,9 @@ and this package never imports them.
 Contents
 --------
 * ``lbt1_oracle.c`` (wrapped here): the moments-only LBMTau1 step in plain
-  FP64, following Algorithm 1 of section 2.1 in the paper's direction order.
+  FP64, following Algorithm 1 of section 2.1 in the paper's direction order,
+  and its multiphase form with the Shan-Chen force of Eq. f_sc
+  (``run(..., sc=(G, rho0))``, ``sc_force``).
 * ``bgk``: brute-force stored-population BGK (Eq. lbm) with streaming and
   bounce-back, any tau; at tau = 1 it must agree with the moments-only step
   (Eq. LBMTau1).
@@ -58,6 +60,15 @@ def _load():
     lib.oracle_reduce.restype = ctypes.c_int
     lib.oracle_reduce.argtypes = [ctypes.c_int, ctypes.c_int, _u8p, _dp, _dp, _dp,
                                   _dp, _dp, _dp, _dp]
+    lib.oracle_run_sc.restype = ctypes.c_int
+    lib.oracle_run_sc.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint, _u8p,
+                                  ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                  ctypes.c_int, ctypes.c_long, _dp, _dp, _dp]
+    lib.oracle_sc_force.restype = ctypes.c_int
+    lib.oracle_sc_force.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint, _u8p,
+                                    ctypes.c_double, ctypes.c_double, _dp, _dp, _dp]
+    lib.oracle_sc_psi.restype = ctypes.c_double
+    lib.oracle_sc_psi.argtypes = [ctypes.c_double, ctypes.c_double]
     lib.oracle_set_threads.argtypes = [ctypes.c_int]
     lib.oracle_get_threads.restype = ctypes.c_int
     _lib = lib
@@ -136,8 +147,9 @@ def step(rho, jx, jy, flags=None, periodic=0, force=(0.0, 0.0), wall=WALL_PAPER)
     return ro, uo, vo
 
 
-def run(rho, jx, jy, nsteps, flags=None, periodic=0, force=(0.0, 0.0), wall=WALL_PAPER):
-    """``nsteps`` LBMTau1 steps; returns new (rho, jx, jy) (inputs untouched)."""
+def run(rho, jx, jy, nsteps, flags=None, periodic=0, force=(0.0, 0.0), wall=WALL_PAPER, sc=None):
+    """``nsteps`` LBMTau1 steps; returns new (rho, jx, jy) (inputs untouched).
+    ``sc=(G, rho0)``: multiphase steps with the Shan-Chen force."""
     rho = np.asarray(rho)
     shape = rho.shape
     ny, nx = shape
@@ -145,11 +157,34 @@ def run(rho, jx, jy, nsteps, flags=None, periodic=0, force=(0.0, 0.0), wall=WALL
     u = np.array(_f64(jx, shape), copy=True)
     v = np.array(_f64(jy, shape), copy=True)
     f = _flags(flags, shape)
-    rc = _load().oracle_run(nx, ny, int(periodic), _fptr(f), float(force[0]), float(force[1]),
-                            int(wall), int(nsteps), _ptr(r), _ptr(u), _ptr(v))
+    if sc is None:
+        rc = _load().oracle_run(nx, ny, int(periodic), _fptr(f), float(force[0]), float(force[1]),
+                                int(wall), int(nsteps), _ptr(r), _ptr(u), _ptr(v))
+    else:
+        rc = _load().oracle_run_sc(nx, ny, int(periodic), _fptr(f), float(force[0]), float(force[1]),
+                                   float(sc[0]), float(sc[1]), int(wall), int(nsteps),
+                                   _ptr(r), _ptr(u), _ptr(v))
     if rc:
         raise ValueError(f"oracle_run failed ({rc})")
     return r, u, v
+
+
+def sc_psi(rho, rho0=1.0):
+    return _load().oracle_sc_psi(float(rho), float(rho0))
+
+
+def sc_force(rho, flags=None, periodic=0, G=-5.0, rho0=1.0):
+    """Shan-Chen force (Fx, Fy) of every node for density ``rho``."""
+    rho = np.asarray(rho)
+    shape = rho.shape
+    ny, nx = shape
+    r = _f64(rho, shape)
+    f = _flags(flags, shape)
+    FX, FY = np.empty(shape), np.empty(shape)
+    rc = _load().oracle_sc_force(nx, ny, int(periodic), _fptr(f), float(G), float(rho0), _ptr(r), _ptr(FX), _ptr(FY))
+    if rc:
+        raise ValueError("oracle_sc_force failed")
+    return FX, FY
 
 
 def reduce(rho, jx, jy, flags=None, snapshot=None):

@@ -21,6 +21,11 @@ Conventions (the same problem statement as the moments-only oracle):
     reversed (half-way bounce-back).
   * FIXED nodes hold their moments, emit the equilibrium of those moments
     every step and absorb whatever arrives.
+  * multiphase (``sc=(G, rho0)``): the Shan-Chen force of the paper's
+    Eq. f_sc, -G psi(x) sum_k w_k psi(x + e_k) e_k with psi(rho) =
+    rho0 (1 - exp(-rho / rho0)), is added to F at every non-solid node; a
+    solid neighbour contributes the psi of its given density, a neighbour
+    outside a non-periodic axis that of the node itself.
 """
 import numpy as np
 
@@ -56,7 +61,7 @@ class BGK:
     """Stored-population D2Q9 BGK on an [ny, nx] grid."""
 
     def __init__(self, rho, jx, jy, flags=None, periodic=0, force=(0.0, 0.0),
-                 wall=WALL_PAPER, tau=1.0):
+                 wall=WALL_PAPER, tau=1.0, sc=None):
         rho = np.array(rho, dtype=np.float64)
         self.ny, self.nx = rho.shape
         self.flags = (np.zeros(rho.shape, np.uint8) if flags is None
@@ -65,6 +70,7 @@ class BGK:
         self.F = (float(force[0]), float(force[1]))
         self.wall = int(wall)
         self.tau = float(tau)
+        self.sc = None if sc is None else (float(sc[0]), float(sc[1]))
         jx = np.array(jx, dtype=np.float64)
         jy = np.array(jy, dtype=np.float64)
         # Any populations carrying these moments will do at tau = 1; the
@@ -101,10 +107,45 @@ class BGK:
         jx[solid], jy[solid] = self._solid_j
         return rho, jx, jy
 
+    def _psi(self, rho):
+        G, rho0 = self.sc
+        return rho0 * (1.0 - np.exp(-rho / rho0))
+
+    def _sc_force_loops(self, rho):
+        """Per-node Shan-Chen force, written with loops over nodes and links."""
+        G, _ = self.sc
+        psi = self._psi(rho)
+        FX = np.zeros(rho.shape)
+        FY = np.zeros(rho.shape)
+        for j in range(self.ny):
+            for i in range(self.nx):
+                if self.flags[j, i] == SOLID:
+                    continue
+                sx = sy = 0.0
+                for k in range(1, 9):
+                    t = self._target(i, j, k)
+                    p = psi[j, i] if t is None else psi[t]
+                    sx += W[k] * p * EX[k]
+                    sy += W[k] * p * EY[k]
+                FX[j, i] = -G * psi[j, i] * sx
+                FY[j, i] = -G * psi[j, i] * sy
+        return FX, FY
+
+    def _force(self, rho, arrays):
+        """Uniform force plus, for multiphase runs, the Shan-Chen force."""
+        fx = np.full(rho.shape, self.F[0])
+        fy = np.full(rho.shape, self.F[1])
+        if self.sc is not None:
+            FX, FY = self._sc_force_arrays(rho) if arrays else self._sc_force_loops(rho)
+            fx = fx + FX
+            fy = fy + FY
+        return fx, fy
+
     def step(self):
         rho, jx, jy = self.moments()
-        ux = (jx + self.tau * self.F[0]) / np.where(self.flags == SOLID, 1.0, rho)
-        uy = (jy + self.tau * self.F[1]) / np.where(self.flags == SOLID, 1.0, rho)
+        fx, fy = self._force(rho, arrays=False)
+        ux = (jx + self.tau * fx) / np.where(self.flags == SOLID, 1.0, rho)
+        uy = (jy + self.tau * fy) / np.where(self.flags == SOLID, 1.0, rho)
         feq = equilibrium(rho, ux, uy)
         post = self.f - (self.f - feq) / self.tau          # Eq. lbm, collision
         fixed = self.flags == FIXED
@@ -165,10 +206,37 @@ class BGK:
         self._links = links
         return links
 
+    def _sc_force_arrays(self, rho):
+        G, _ = self.sc
+        psi = self._psi(rho)
+        ny, nx = self.ny, self.nx
+        jj, ii = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+        sx = np.zeros(rho.shape)
+        sy = np.zeros(rho.shape)
+        for k in range(1, 9):
+            ip, jp = ii + EX[k], jj + EY[k]
+            inside = np.ones((ny, nx), bool)
+            if self.periodic & 1:
+                ip = ip % nx
+            else:
+                inside &= (ip >= 0) & (ip < nx)
+            if self.periodic & 2:
+                jp = jp % ny
+            else:
+                inside &= (jp >= 0) & (jp < ny)
+            p = np.where(inside, psi[np.clip(jp, 0, ny - 1), np.clip(ip, 0, nx - 1)], psi)
+            sx = sx + W[k] * p * EX[k]
+            sy = sy + W[k] * p * EY[k]
+        solid = self.flags == SOLID
+        FX = np.where(solid, 0.0, -G * psi * sx)
+        FY = np.where(solid, 0.0, -G * psi * sy)
+        return FX, FY
+
     def step_arrays(self):
         rho, jx, jy = self.moments()
-        ux = (jx + self.tau * self.F[0]) / np.where(self.flags == SOLID, 1.0, rho)
-        uy = (jy + self.tau * self.F[1]) / np.where(self.flags == SOLID, 1.0, rho)
+        fx, fy = self._force(rho, arrays=True)
+        ux = (jx + self.tau * fx) / np.where(self.flags == SOLID, 1.0, rho)
+        uy = (jy + self.tau * fy) / np.where(self.flags == SOLID, 1.0, rho)
         feq = equilibrium(rho, ux, uy)
         post = self.f - (self.f - feq) / self.tau
         fixed = self.flags == FIXED

@@ -30,6 +30,14 @@
  *   back reversed) is provided as the alternative reading.
  *   nodes flagged FIXED (the moving lid of Appendix A) act as sources with
  *   their stored moments and are never updated.
+ *   multiphase (section "Moments-only multirelaxation time LBMTau1"): the
+ *   Shan-Chen interaction force of Eq. f_sc, F(x) = psi(x) sum_k alpha_k
+ *   psi(x + e_k) G(e_k), read with alpha_k = w_k and G(e_k) = -G e_k and the
+ *   pseudopotential psi(rho) = rho0 (1 - exp(-rho / rho0)) of the Shan-Chen
+ *   model the paper cites; at tau = 1 it enters the equilibrium of its node
+ *   exactly like the body force.  A SOLID neighbour contributes the psi of
+ *   its stored density; a neighbour outside a non-periodic axis that of the
+ *   node itself.
  *
  * Summation follows the paper's direction order k = 0..8 and its arithmetic
  * form w * r * (1 - 3/2 |u|^2 + 3 e.u + 9/2 (e.u)^2).  Build with
@@ -96,12 +104,13 @@ int oracle_get_threads(void) { return oracle_threads; }
 /*
  * One LBMTau1 step (Algorithm 1).  Arrays are ny*nx, x fastest.
  * flags == NULL means every node is FLUID.  Non-FLUID nodes are copied.
- * Returns 0, or -1 on bad arguments.
+ * FX, FY (optional, ny*nx): a force per node added to the uniform (fx, fy)
+ * of the source node.  Returns 0, or -1 on bad arguments.
  */
-int oracle_step(int nx, int ny, unsigned periodic, const uint8_t *flags,
-                double fx, double fy, int wall, const double *R,
-                const double *U, const double *V, double *Rn, double *Un,
-                double *Vn) {
+static int step_forced(int nx, int ny, unsigned periodic, const uint8_t *flags,
+                       double fx, double fy, const double *FX, const double *FY,
+                       int wall, const double *R, const double *U,
+                       const double *V, double *Rn, double *Un, double *Vn) {
   if (nx < 1 || ny < 1 || !R || !U || !V || !Rn || !Un || !Vn) return -1;
   if (wall != OR_WALL_PAPER && wall != OR_WALL_HALFWAY) return -1;
 #ifdef _OPENMP
@@ -124,16 +133,20 @@ int oracle_step(int nx, int ny, unsigned periodic, const uint8_t *flags,
         int solid = (s < 0) || (flags && flags[s] == OR_SOLID);
         double f;
         if (!solid) {
+          double gx = FX ? fx + FX[s] : fx;
+          double gy = FY ? fy + FY[s] : fy;
           double r = R[s];
-          double u = (U[s] + fx) / r;
-          double v = (V[s] + fy) / r;
+          double u = (U[s] + gx) / r;
+          double v = (V[s] + gy) / r;
           f = oracle_feq(ik, r, u, v);
         } else if (wall == OR_WALL_PAPER) {
           f = OR_W[ik] * R[x];
         } else {
+          double gx = FX ? fx + FX[x] : fx;
+          double gy = FY ? fy + FY[x] : fy;
           double r = R[x];
-          double u = (U[x] + fx) / r;
-          double v = (V[x] + fy) / r;
+          double u = (U[x] + gx) / r;
+          double v = (V[x] + gy) / r;
           f = oracle_feq(k, r, u, v);
         }
         rs += f;
@@ -148,14 +161,77 @@ int oracle_step(int nx, int ny, unsigned periodic, const uint8_t *flags,
   return 0;
 }
 
+int oracle_step(int nx, int ny, unsigned periodic, const uint8_t *flags,
+                double fx, double fy, int wall, const double *R,
+                const double *U, const double *V, double *Rn, double *Un,
+                double *Vn) {
+  return step_forced(nx, ny, periodic, flags, fx, fy, NULL, NULL, wall, R, U,
+                     V, Rn, Un, Vn);
+}
+
+/* Shan-Chen pseudopotential. */
+double oracle_sc_psi(double r, double rho0) { return rho0 * (1.0 - exp(-r / rho0)); }
+
+/*
+ * Shan-Chen force of every FLUID and FIXED node (Eq. f_sc with alpha_k = w_k,
+ * G(e_k) = -G e_k):  F(x) = -G psi(x) sum_{k=1..8} w_k psi(x + e_k) e_k.
+ * FX, FY receive ny*nx values (0 at SOLID nodes).  Returns 0 or -1.
+ */
+int oracle_sc_force(int nx, int ny, unsigned periodic, const uint8_t *flags,
+                    double G, double rho0, const double *R, double *FX,
+                    double *FY) {
+  if (nx < 1 || ny < 1 || !R || !FX || !FY || !(rho0 > 0.0)) return -1;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static) num_threads(oracle_threads)
+#endif
+  for (int j = 0; j < ny; ++j) {
+    for (int i = 0; i < nx; ++i) {
+      long x = (long)j * nx + i;
+      if (flags && flags[x] == OR_SOLID) {
+        FX[x] = 0.0;
+        FY[x] = 0.0;
+        continue;
+      }
+      double px = oracle_sc_psi(R[x], rho0);
+      double sx = 0.0, sy = 0.0;
+      for (int k = 1; k < 9; ++k) {
+        long s = neighbour(nx, ny, periodic, i, j, k);
+        double pk = s < 0 ? px : oracle_sc_psi(R[s], rho0);
+        sx += OR_W[k] * pk * OR_EX[k];
+        sy += OR_W[k] * pk * OR_EY[k];
+      }
+      FX[x] = -G * px * sx;
+      FY[x] = -G * px * sy;
+    }
+  }
+  return 0;
+}
+
+/* One multiphase step: the Shan-Chen force of the current state, then the
+ * LBMTau1 step with it added to the uniform force. */
+int oracle_step_sc(int nx, int ny, unsigned periodic, const uint8_t *flags,
+                   double fx, double fy, double G, double rho0, int wall,
+                   const double *R, const double *U, const double *V,
+                   double *Rn, double *Un, double *Vn) {
+  size_t n = (size_t)nx * (size_t)ny;
+  double *F = (double *)malloc(2 * n * sizeof(double));
+  if (!F) return -2;
+  int rc = oracle_sc_force(nx, ny, periodic, flags, G, rho0, R, F, F + n);
+  if (!rc)
+    rc = step_forced(nx, ny, periodic, flags, fx, fy, F, F + n, wall, R, U, V,
+                     Rn, Un, Vn);
+  free(F);
+  return rc;
+}
+
 /*
  * n steps in place on (R, U, V), ping-ponging through a scratch copy
  * (the two grids of Algorithm 1).  Returns 0, -1 on bad arguments,
  * -2 when scratch memory cannot be had.
  */
-int oracle_run(int nx, int ny, unsigned periodic, const uint8_t *flags,
-               double fx, double fy, int wall, long nsteps, double *R,
-               double *U, double *V) {
+static int run_impl(int nx, int ny, unsigned periodic, const uint8_t *flags,
+                    double fx, double fy, int sc, double G, double rho0,
+                    int wall, long nsteps, double *R, double *U, double *V) {
   if (nsteps < 0) return -1;
   if (nsteps == 0) return 0;
   size_t n = (size_t)nx * (size_t)ny;
@@ -164,8 +240,10 @@ int oracle_run(int nx, int ny, unsigned periodic, const uint8_t *flags,
   double *a[3] = {R, U, V};
   double *b[3] = {buf, buf + n, buf + 2 * n};
   for (long t = 0; t < nsteps; ++t) {
-    int rc = oracle_step(nx, ny, periodic, flags, fx, fy, wall, a[0], a[1],
-                         a[2], b[0], b[1], b[2]);
+    int rc = sc ? oracle_step_sc(nx, ny, periodic, flags, fx, fy, G, rho0,
+                                 wall, a[0], a[1], a[2], b[0], b[1], b[2])
+                : oracle_step(nx, ny, periodic, flags, fx, fy, wall, a[0],
+                              a[1], a[2], b[0], b[1], b[2]);
     if (rc) {
       free(buf);
       return rc;
@@ -183,6 +261,20 @@ int oracle_run(int nx, int ny, unsigned periodic, const uint8_t *flags,
   }
   free(buf);
   return 0;
+}
+
+int oracle_run(int nx, int ny, unsigned periodic, const uint8_t *flags,
+               double fx, double fy, int wall, long nsteps, double *R,
+               double *U, double *V) {
+  return run_impl(nx, ny, periodic, flags, fx, fy, 0, 0.0, 1.0, wall, nsteps,
+                  R, U, V);
+}
+
+int oracle_run_sc(int nx, int ny, unsigned periodic, const uint8_t *flags,
+                  double fx, double fy, double G, double rho0, int wall,
+                  long nsteps, double *R, double *U, double *V) {
+  return run_impl(nx, ny, periodic, flags, fx, fy, 1, G, rho0, wall, nsteps, R,
+                  U, V);
 }
 
 /*

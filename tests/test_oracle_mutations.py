@@ -15,7 +15,7 @@ MUTATIONS = {
     "wrong_sign_u2": ("1.0 - 1.5 * (u * u + v * v)", "1.0 + 1.5 * (u * u + v * v)"),
     "momentum_uses_k_not_inverse": ("us += OR_EX[ik] * f;", "us += OR_EX[k] * f;"),
     "paper_wall_drops_density": ("f = OR_W[ik] * R[x];", "f = OR_W[ik] * 1.0;"),
-    "force_not_applied": ("double u = (U[s] + fx) / r;", "double u = U[s] / r;"),
+    "force_not_applied": ("double u = (U[s] + gx) / r;", "double u = U[s] / r;"),
     "halfway_returns_wrong_direction": ("f = oracle_feq(k, r, u, v);", "f = oracle_feq(ik, r, u, v);"),
     "periodic_wrap_transposed": ("ip = (ip + nx) % nx;", "ip = (ip + ny) % ny;"),
     "eu_uses_u_twice": ("double eu = OR_EX[k] * u + OR_EY[k] * v;", "double eu = OR_EX[k] * u + OR_EY[k] * u;"),
@@ -24,6 +24,9 @@ MUTATIONS = {
     "source_density_from_target": ("double r = R[s];", "double r = R[x];"),
     "inverse_table_swapped": ("{0, 3, 4, 1, 2, 7, 8, 5, 6}", "{0, 3, 4, 1, 2, 8, 7, 5, 6}"),
     "diagonal_weight": ("1.0 / 36.0, 1.0 / 36.0};", "1.0 / 36.0, 1.0 / 9.0};"),
+    "sc_force_uses_wrong_component": ("sy += OR_W[k] * pk * OR_EY[k];", "sy += OR_W[k] * pk * OR_EX[k];"),
+    "sc_force_without_own_psi": ("FX[x] = -G * px * sx;", "FX[x] = -G * sx;"),
+    "sc_psi_sign": ("rho0 * (1.0 - exp(-r / rho0))", "rho0 * (1.0 + exp(-r / rho0))"),
 }
 
 

@@ -17,6 +17,10 @@ P9  memory formulas                   -- tests/golden/memory_example.txt
 P10 stored-population BGK, any tau    -- array form = loop form; linear theory of the
                                          shear mode (9 x 9 eigenproblem); viscosity
                                          (tau - 1/2)/3; exact steady parabola; conservation
+P11 multiphase (Shan-Chen force)       -- brute-force BGK with the force at tau = 1; pair
+                                         antisymmetry (momentum conserved); flat-interface
+                                         coexistence against the mechanical-stability
+                                         integral; Laplace law; G = 0 is the plain step
 """
 import math
 import os
@@ -486,3 +490,100 @@ def test_p10_bgk_periodic_conservation(tau):
     assert abs(r.sum() - M0) <= 8 * EPS * n * M0
     assert x.sum() == pytest.approx(X0 + n * nx * ny * F[0], abs=1e-12)
     assert y.sum() == pytest.approx(Y0 + n * nx * ny * F[1], abs=1e-12)
+
+
+# ----------------------------------------------------------------- P11 multiphase
+def _sc_state(rng, ny, nx):
+    rho = 1.0 + 0.4 * rng.random((ny, nx))
+    return rho, 0.01 * rng.standard_normal((ny, nx)), 0.01 * rng.standard_normal((ny, nx))
+
+
+@pytest.mark.parametrize("periodic", [0, 3])
+@pytest.mark.parametrize("wall", [oracle.WALL_PAPER, oracle.WALL_HALFWAY])
+def test_p11_bgk_tau1_with_shan_chen_force_equals_moments_only(periodic, wall):
+    """Section "Moments-only multirelaxation time LBMTau1": at tau = 1 the populations
+    leaving a node are the equilibria of its moments and its Shan-Chen force, so the
+    stored-population solver (written independently, loops) and the moments-only
+    oracle agree to rounding."""
+    rng = _rng(90 + periodic)
+    ny, nx = 9, 11
+    rho, jx, jy = _sc_state(rng, ny, nx)
+    flags = (rng.random((ny, nx)) < 0.1).astype(np.uint8)
+    ref = bgk.BGK(rho, jx, jy, flags, periodic, (1e-4, 0.0), wall, 1.0, sc=(-5.0, 1.0))
+    for _ in range(12):
+        ref.step()
+    got = oracle.run(rho, jx, jy, 12, flags, periodic, (1e-4, 0.0), wall, sc=(-5.0, 1.0))
+    fl = flags == oracle.FLUID
+    for a, b in zip(got, ref.moments()):
+        assert np.abs(a - b)[fl].max() < 5e-15
+
+
+def test_p11_shan_chen_pair_forces_cancel():
+    """Eq. f_sc: the force between x and x + e_k is -G w_k psi(x) psi(x + e_k) e_k and
+    its reverse, so in a periodic domain the forces sum to zero and the total momentum
+    of a run is conserved (mass too)."""
+    rng = _rng(93)
+    ny, nx = 17, 23
+    rho, jx, jy = _sc_state(rng, ny, nx)
+    FX, FY = oracle.sc_force(rho, None, 3, -5.5, 1.0)
+    scale = np.abs(FX).sum() + np.abs(FY).sum()
+    assert abs(FX.sum()) < 1e-14 * scale and abs(FY.sum()) < 1e-14 * scale
+    r, u, v = oracle.run(rho, jx, jy, 150, None, 3, (0.0, 0.0), 0, sc=(-5.5, 1.0))
+    assert abs(r.sum() - rho.sum()) <= 8 * EPS * 150 * rho.sum()
+    assert abs(u.sum() - jx.sum()) < 1e-12 and abs(v.sum() - jy.sum()) < 1e-12
+    # G = 0: the plain step, bit for bit
+    a = oracle.run(rho, jx, jy, 7, None, 3, (1e-5, 0.0), 0, sc=(0.0, 1.0))
+    b = oracle.run(rho, jx, jy, 7, None, 3, (1e-5, 0.0), 0)
+    assert all(np.array_equal(x, y) for x, y in zip(a, b))
+
+
+def _coexistence_theory(G, rho0=1.0):
+    """Shan-Chen coexistence densities: p(rho_g) = p(rho_l) and the mechanical-stability
+    integral of (p0 - p) psi' / psi^2 from rho_g to rho_l vanishes, with the pressure
+    p = rho/3 + G psi^2 / 6 of the D2Q9 force weights (scipy quadrature and root)."""
+    from scipy.integrate import quad
+    from scipy.optimize import fsolve
+    psi = lambda r: rho0 * (1 - np.exp(-r / rho0))
+    dpsi = lambda r: np.exp(-r / rho0)
+    p = lambda r: r / 3 + G * psi(r) ** 2 / 6
+
+    def eqs(v):
+        g, l = v
+        return [p(g) - p(l), quad(lambda r: (p(g) - p(r)) * dpsi(r) / psi(r) ** 2, g, l, limit=200)[0]]
+    return fsolve(eqs, [0.1, 2.0], xtol=1e-13)
+
+
+@pytest.mark.parametrize("G", [-5.0, -6.0])
+def test_p11_flat_interface_coexistence(G):
+    """A liquid slab in vapour (periodic, x-independent) separates into the coexistence
+    densities of the model's mechanical-stability condition (liquid within 0.2 %, vapour
+    within 1.5 %: the lattice gradients differ from the continuum ones at that level)."""
+    oracle.set_threads(4)
+    g0, l0 = _coexistence_theory(G)
+    ny, nx = 120, 3
+    y = np.arange(ny)
+    prof = g0 + (l0 - g0) * 0.5 * (np.tanh((y - 30) / 3) - np.tanh((y - 90) / 3))
+    rho = np.repeat(prof[:, None], nx, 1)
+    z = np.zeros_like(rho)
+    r, _, _ = oracle.run(rho, z, z, 40000, None, 3, (0.0, 0.0), 0, sc=(G, 1.0))
+    assert abs(r.max() / l0 - 1) < 2e-3
+    assert abs(r.min() / g0 - 1) < 1.5e-2
+
+
+def test_p11_laplace_law():
+    """Static drops: the pressure jump times the radius (the surface tension) is the
+    same for radii 12, 16 and 20 within 2 %, with p = rho/3 + G psi^2 / 6."""
+    oracle.set_threads(4)
+    G, L = -5.5, 72
+    p = lambda r: r / 3 + G * (1 - np.exp(-r)) ** 2 / 6
+    sig = []
+    for R0 in (12, 16, 20):
+        y, x = np.mgrid[0:L, 0:L]
+        d = np.hypot(x - L / 2 + 0.5, y - L / 2 + 0.5)
+        rho = 0.104 + (2.307 - 0.104) * 0.5 * (1 - np.tanh((d - R0) / 2))
+        z = np.zeros_like(rho)
+        r, _, _ = oracle.run(rho, z, z, 8000, None, 3, (0.0, 0.0), 0, sc=(G, 1.0))
+        radius = np.sqrt((r > (r.max() + r.min()) / 2).sum() / np.pi)
+        sig.append((p(r[L // 2, L // 2]) - p(r[0, 0])) * radius)
+    assert max(sig) / min(sig) - 1 < 0.02, sig
+    assert 0.08 < np.mean(sig) < 0.11
