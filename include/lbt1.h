@@ -89,7 +89,7 @@ enum {
                              the three rows of each lattice row are adjacent in memory
                              ([ny][3][pitch]), so a row is one contiguous read and one
                              contiguous write */
-  LBT1_OPT_POPULATIONS = 4u /* the standard stored-population D2Q9 BGK method instead of
+  LBT1_OPT_POPULATIONS = 4u, /* the standard stored-population D2Q9 BGK method instead of
                              LBMTau1 (section 2, Eq. lbm, with relaxation time
                              lbt1_grid_desc.tau): two parities of nine population fields,
                              each stored as the deviation f_q - w_q in the grid's storage
@@ -98,6 +98,16 @@ enum {
                              force rules; the equilibrium velocity is (j + tau F) / rho.
                              lbt1_step runs one kernel (set_kernel/autotune: EINVAL); the
                              grid cannot join a batch */
+  LBT1_OPT_MULTIPHASE = 8u  /* single-component multiphase flow: the Shan-Chen interaction
+                             force of the paper's Eq. f_sc, F(x) = -G psi(x) sum_k w_k
+                             psi(x + e_k) e_k with psi(rho) = rho0 (1 - exp(-rho / rho0))
+                             (lbt1_grid_desc.sc_G, sc_rho0), is added to the body force of
+                             every node before its equilibrium is formed.  A SOLID
+                             neighbour contributes the psi of its stored density (a
+                             wetting control), a neighbour outside a non-periodic axis that
+                             of the node itself.  No FIXED nodes (EINVAL); no batches.
+                             LBMTau1 grids keep no psi field (it is formed in registers);
+                             population grids keep one psi value per node */
 };
 
 /* lbt1_reduce what-mask bits and output slots */
@@ -130,6 +140,9 @@ typedef struct {
   void *stream;          /* hipStream_t to run on; NULL: a library-owned stream */
   double tau;            /* relaxation time of LBT1_OPT_POPULATIONS grids, > 1/2 (0 means
                             1); other grids are LBMTau1 (tau = 1): 0 or 1 only */
+  double sc_G;           /* LBT1_OPT_MULTIPHASE: Shan-Chen coupling G (finite; negative is
+                            attractive, phase separation below about -4); 0 otherwise */
+  double sc_rho0;        /* LBT1_OPT_MULTIPHASE: psi scale rho0 > 0 (0 means 1) */
 } lbt1_grid_desc;
 
 /* Device bytes a grid of this shape needs: two parities of the three moment

@@ -26,6 +26,7 @@ PERIODIC_X, PERIODIC_Y = 1, 2
 OPT_SNAPSHOT = 1
 OPT_PLANAR = 2
 OPT_POPULATIONS = 4
+OPT_MULTIPHASE = 8
 REDUCE_MASS, REDUCE_MOMENTUM, REDUCE_RESIDUAL, REDUCE_NONFINITE = 1, 2, 4, 8
 REDUCE_ALL = 15
 REDUCE_SLOTS = 6
@@ -48,6 +49,7 @@ class GridDesc(ctypes.Structure):
         ("force", ctypes.c_double * 2), ("scale", ctypes.c_double * 2),
         ("device_buffer", ctypes.c_void_p), ("device_bytes", ctypes.c_size_t),
         ("stream", ctypes.c_void_p), ("tau", ctypes.c_double),
+        ("sc_G", ctypes.c_double), ("sc_rho0", ctypes.c_double),
     ]
 
 

@@ -37,6 +37,10 @@ struct BgkArgs {
   double sc, is;        // decode / encode scale of the populations
   int tiles_x, tiles;   // 64 x 4 node tiles per tile row / in all
   int per_xcd;          // consecutive tiles per XCD (launch: 8 * per_xcd blocks)
+  // multiphase: psi of every node (arithmetic type, [ny][pitch]), written by
+  // k_bgk_psi before each step; the force is tau (F_body + F_SC)
+  void *psi;
+  double sc_G, sc_rho0, tau, bfx, bfy;
 };
 
 struct BgkReduceArgs {

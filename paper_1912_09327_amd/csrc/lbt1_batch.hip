@@ -325,6 +325,7 @@ lbt1_status lbt1_batch_admit(lbt1_batch *b, lbt1_grid *g, int64_t step_budget, d
   if (g->batch) return fail(LBT1_ESTATE, "grid is already resident in a batch");
   if (!g->geometry) return fail(LBT1_ESTATE, "grid geometry is not set");
   if (g->pop) return fail(LBT1_EINVAL, "population grids (LBT1_OPT_POPULATIONS) cannot join a batch");
+  if (g->mp) return fail(LBT1_EINVAL, "multiphase grids (LBT1_OPT_MULTIPHASE) cannot join a batch");
   if (!g->snap[0]) return fail(LBT1_EINVAL, "batched grids need LBT1_OPT_SNAPSHOT");
   if (g->device != b->device) return fail(LBT1_EINVAL, "grid is on another device");
   if (b->prec >= 0 && g->prec != b->prec) return fail(LBT1_EINVAL, "batch precision is %d, grid has %d", b->prec, g->prec);

@@ -22,7 +22,38 @@ namespace lbt1 {
 // XCDs, each with its own L2; the tiles are dealt out so that one XCD works
 // on a contiguous run of tiles along the rows, and the stores that spill one
 // node past a tile edge meet the neighbouring tile's stores in the same L2.
-template <int P, bool HASWALL, int WALL>
+// rho - 1 of a node from its nine deviations (the order every kernel uses)
+template <typename C>
+__device__ __forceinline__ C pop_density(const C (&g)[9]) {
+  return (((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + (g[6] + g[7]))) + g[8];
+}
+
+// Multiphase: the pseudopotential of every node (SOLID nodes hold the
+// zero-velocity equilibrium of their given density, so theirs is that of the
+// given density).
+template <int P>
+__global__ void __launch_bounds__(256) k_bgk_psi(BgkArgs a) {
+  using T = Traits<P>;
+  using C = typename T::C;
+  using S = typename T::S;
+  const int t = (blockIdx.x & 7) * a.per_xcd + (blockIdx.x >> 3);
+  if (t >= a.tiles) return;
+  const int by = t / a.tiles_x;
+  const int x = (t - by * a.tiles_x) * 64 + (threadIdx.x & 63);
+  const int y = by * 4 + (threadIdx.x >> 6);
+  if (x >= a.nx || y >= a.ny) return;
+  const long i = (long)y * a.rs + x;
+  C g[9];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    g[q] = T::dec(static_cast<const S *>(a.src[q])[i]);
+    if (T::kScaled) g[q] *= C(a.sc);
+  }
+  static_cast<C *>(a.psi)[(long)y * a.pitch + x] =
+      sc_psi<C>(C(1) + pop_density<C>(g), C(a.sc_rho0), C(1.0 / a.sc_rho0));
+}
+
+template <int P, bool HASWALL, int WALL, bool SC>
 __global__ void __launch_bounds__(256) k_bgk_step(BgkArgs a) {
   using T = Traits<P>;
   using C = typename T::C;
@@ -47,13 +78,29 @@ __global__ void __launch_bounds__(256) k_bgk_step(BgkArgs a) {
     if (T::kScaled) g[q] *= sc;
   }
   // moments of the deviations: rho - 1 = sum g, j = sum e g (sum w e = 0)
-  const C d = (((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + (g[6] + g[7]))) + g[8];
+  const C d = pop_density<C>(g);
   const C jx = ((g[1] - g[3]) + (g[5] - g[6])) + (g[8] - g[7]);
   const C jy = ((g[2] - g[4]) + (g[5] - g[7])) + (g[6] - g[8]);
   C post[9];
   if (!HASWALL || fl == NODE_FLUID) {
+    C Fx = C(a.fx), Fy = C(a.fy);
+    if (SC) {
+      const C *ps = static_cast<const C *>(a.psi);
+      C psi[9];
+      psi[0] = ps[(long)y * a.pitch + x];
+#pragma unroll
+      for (int k = 1; k < 9; ++k) {
+        const int tx = wrap_axis(x + kEx[k], a.nx, a.periodic & 1u);
+        const int ty = wrap_axis(y + kEy[k], a.ny, a.periodic & 2u);
+        psi[k] = (tx < 0 || ty < 0) ? psi[0] : ps[(long)ty * a.pitch + tx];
+      }
+      C gx, gy;
+      sc_force<C>(psi, C(a.sc_G), gx, gy);
+      Fx = C(a.tau) * (C(a.bfx) + gx);
+      Fy = C(a.tau) * (C(a.bfy) + gy);
+    }
     C geq[9];
-    emit<C>(d, jx, jy, C(a.fx), C(a.fy), geq);
+    emit<C>(d, jx, jy, Fx, Fy, geq);
     const C om = C(a.omega);
 #pragma unroll
     for (int q = 0; q < 9; ++q) post[q] = fmaC<C>(om, geq[q] - g[q], g[q]);

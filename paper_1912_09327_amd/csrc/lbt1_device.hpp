@@ -112,6 +112,27 @@ __device__ __forceinline__ void emit(C d, C jx, C jy, C Fx, C Fy, C f[9]) {
 template <typename C> __device__ __forceinline__ C wall_axis(C d) { return C(1.0 / 9.0) * d; }
 template <typename C> __device__ __forceinline__ C wall_diag(C d) { return C(1.0 / 36.0) * d; }
 
+// ----------------------------------------------------------------- multiphase
+// Shan-Chen pseudopotential psi(rho) = rho0 (1 - exp(-rho / rho0)).
+template <typename C> __device__ inline C sc_exp(C x);
+template <> __device__ inline float sc_exp<float>(float x) { return expf(x); }
+template <> __device__ inline double sc_exp<double>(double x) { return exp(x); }
+template <typename C>
+__device__ __forceinline__ C sc_psi(C rho, C rho0, C inv_rho0) {
+  return rho0 * (C(1) - sc_exp<C>(-rho * inv_rho0));
+}
+// Interaction force of a node (the paper's Eq. f_sc with alpha_k = w_k and
+// G(e_k) = -G e_k): F = -G psi_0 sum_k w_k psi_k e_k, psi_0 the node's own
+// pseudopotential and psi_k that of its neighbour along e_k.
+template <typename C>
+__device__ __forceinline__ void sc_force(const C (&psi)[9], C G, C &fx, C &fy) {
+  const C sx = C(1.0 / 9.0) * (psi[1] - psi[3]) + C(1.0 / 36.0) * ((psi[5] - psi[6]) + (psi[8] - psi[7]));
+  const C sy = C(1.0 / 9.0) * (psi[2] - psi[4]) + C(1.0 / 36.0) * ((psi[5] - psi[7]) + (psi[6] - psi[8]));
+  const C a = -G * psi[0];
+  fx = a * sx;
+  fy = a * sy;
+}
+
 // ----------------------------------------------------------------- target sums
 // Arrivals g[q] at a node (g[q] travelled along e_q, from x - e_q).  Grouped
 // by the source row: y-1 (q = 5, 2, 6), y (1, 0, 3), y+1 (8, 4, 7).  This
@@ -140,6 +161,7 @@ struct StepArgs {
   double is_d, is_j;   // encode scales (value * is = stored)
   void *trash;         // 3 KiB of device scratch: target of the stores of lanes and
                        // rows outside the grid, so that stores need no branch
+  double sc_G, sc_rho0;  // multiphase kernels: Shan-Chen coupling and psi scale
 };
 
 // Source coordinate along one axis: wrapped when periodic (any distance, so

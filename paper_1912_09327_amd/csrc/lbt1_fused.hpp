@@ -30,20 +30,22 @@ struct FusedStage {
   ArrS<C, VEC> upA, upB, lev;
 };
 
-// One source row into stage `st` (values already decoded and scaled).  When
-// `emit_row` (the stage has seen two earlier rows), the target row one above
-// is completed into dn/jxn/jyn (unscaled arithmetic values).
+// One source row into stage `st` (values already decoded and scaled; Fx, Fy
+// the force of each source column).  When `emit_row` (the stage has seen two
+// earlier rows), the target row one above is completed into dn/jxn/jyn
+// (unscaled arithmetic values).
 template <int P, int VEC>
 __device__ __forceinline__ void fused_feed(FusedStage<P, VEC> &st, const bool odd, const bool emit_row,
                                            const typename Traits<P>::C (&d)[VEC],
                                            const typename Traits<P>::C (&jx)[VEC],
-                                           const typename Traits<P>::C (&jy)[VEC], const typename Traits<P>::C Fx,
-                                           const typename Traits<P>::C Fy, typename Traits<P>::C (&dn)[VEC],
+                                           const typename Traits<P>::C (&jy)[VEC],
+                                           const typename Traits<P>::C (&Fx)[VEC],
+                                           const typename Traits<P>::C (&Fy)[VEC], typename Traits<P>::C (&dn)[VEC],
                                            typename Traits<P>::C (&jxn)[VEC], typename Traits<P>::C (&jyn)[VEC]) {
   using C = typename Traits<P>::C;
   C f[VEC][9];
 #pragma unroll
-  for (int v = 0; v < VEC; ++v) emit<C>(d[v], jx[v], jy[v], Fx, Fy, f[v]);
+  for (int v = 0; v < VEC; ++v) emit<C>(d[v], jx[v], jy[v], Fx[v], Fy[v], f[v]);
   const C L1 = __shfl_up(f[VEC - 1][1], 1);
   const C L5 = __shfl_up(f[VEC - 1][5], 1);
   const C L8 = __shfl_up(f[VEC - 1][8], 1);
@@ -87,7 +89,12 @@ __device__ __forceinline__ void fused_body(const StepArgs &a, const int chunk0, 
 
   const int ny = a.ny;
   const long rs = a.rs;
-  const C Fx = C(a.fx), Fy = C(a.fy);
+  C Fx[VEC], Fy[VEC];
+#pragma unroll
+  for (int v = 0; v < VEC; ++v) {
+    Fx[v] = C(a.fx);
+    Fy[v] = C(a.fy);
+  }
   const C sd = C(a.sc_d), sj = C(a.sc_j), ed = C(a.is_d), ej = C(a.is_j);
   const S *__restrict__ s0 = static_cast<const S *>(a.src[0]);
   const S *__restrict__ s1 = static_cast<const S *>(a.src[1]);

@@ -14,13 +14,15 @@ struct StepKernel {
   int prec, haswall, wall, kind, vec, rows;
   const void *fn;
   const char *name;
-  int steps;  // time steps one launch advances (fused strip kernels: 2 or 4)
+  int steps;  // time steps one launch advances (fused strip kernels: 2)
+  int sc;     // multiphase (Shan-Chen force) kernel
 };
 
 const StepKernel *step_kernels(int *count);
 const void *reduce_partial_kernel(int prec);
 const void *reduce_final_kernel();
 const void *bgk_reduce_partial_kernel(int prec);
+const void *bgk_psi_kernel(int prec);
 const void *batch_step_kernel(int prec, int vec_class, int rows);
 const void *batch_reduce_kernel(int prec);
 const void *batch_reduce_final_kernel();

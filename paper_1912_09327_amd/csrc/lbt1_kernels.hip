@@ -3,6 +3,7 @@
 #include "lbt1_internal.hpp"
 #include "lbt1_bgk.hpp"
 #include "lbt1_fused.hpp"
+#include "lbt1_multiphase.hpp"
 #include "lbt1_step.hpp"
 
 namespace lbt1 {
@@ -22,14 +23,14 @@ __global__ void __launch_bounds__(64) k_reduce_final(const double *partials, int
 #define LBT1_STR(x) LBT1_STR2(x)
 
 #define GATHER(P, HW, W) \
-  {P, HW, W, KIND_GATHER, 0, 0, (const void *)&k_step_gather<P, HW, W>, "k_step_gather<" #P "," #HW "," #W ">", 1}
+  {P, HW, W, KIND_GATHER, 0, 0, (const void *)&k_step_gather<P, HW, W>, "k_step_gather<" #P "," #HW "," #W ">", 1, 0}
 #define STRIP(P, HW, W, V, R)                                                    \
   {P, HW, W, KIND_STRIP, V, R, (const void *)&k_step_strip<P, HW, W, V, R>, \
-   "k_step_strip<" #P "," #HW "," #W "," #V "," #R ">", 1}
+   "k_step_strip<" #P "," #HW "," #W "," #V "," #R ">", 1, 0}
 // K steps per launch, fully periodic grids without wall or fixed nodes
 #define FUSED(P, V, R, K)                                                        \
   {P, false, 0, KIND_STRIP, V, R, (const void *)&k_step_fused<P, V, R, K>, \
-   "k_step_fused<" #P "," #V "," #R "," #K ">", K}
+   "k_step_fused<" #P "," #V "," #R "," #K ">", K, 0}
 #define FUSED_ROWS(P, V, K) FUSED(P, V, 6, K), FUSED(P, V, 14, K)
 #define STRIP_WALLS(P, V, R) STRIP(P, false, 0, V, R), STRIP(P, true, 0, V, R), STRIP(P, true, 1, V, R)
 #define STRIP_ROWS(P, V) STRIP_WALLS(P, V, 6), STRIP_WALLS(P, V, 14)
@@ -38,9 +39,18 @@ __global__ void __launch_bounds__(64) k_reduce_final(const double *partials, int
 // kernel that spills or uses scratch memory)
 #define STRIP_ROWS_NOWALL(P, V) STRIP(P, false, 0, V, 6), STRIP(P, false, 0, V, 14)
 #define GATHER_ALL(P) GATHER(P, false, 0), GATHER(P, true, 0), GATHER(P, true, 1)
-#define BGK(P, HW, W) \
-  {P, HW, W, KIND_BGK, 0, 0, (const void *)&k_bgk_step<P, HW, W>, "k_bgk_step<" #P "," #HW "," #W ">", 1}
-#define BGK_ALL(P) BGK(P, false, 0), BGK(P, true, 0), BGK(P, true, 1)
+#define BGK(P, HW, W, SC) \
+  {P, HW, W, KIND_BGK, 0, 0, (const void *)&k_bgk_step<P, HW, W, SC>, "k_bgk_step<" #P "," #HW "," #W "," #SC ">", 1, SC}
+#define BGK_ALL(P)                                                                            \
+  BGK(P, false, 0, false), BGK(P, true, 0, false), BGK(P, true, 1, false), BGK(P, false, 0, true), \
+      BGK(P, true, 0, true), BGK(P, true, 1, true)
+// multiphase LBMTau1: gather for any geometry, strips for periodic grids without walls
+#define SC_GATHER(P, HW, W) \
+  {P, HW, W, KIND_GATHER, 0, 0, (const void *)&k_step_sc_gather<P, HW, W>, "k_step_sc_gather<" #P "," #HW "," #W ">", 1, 1}
+#define SC_STRIP(P, V, R) \
+  {P, false, 0, KIND_STRIP, V, R, (const void *)&k_step_sc_strip<P, V, R>, "k_step_sc_strip<" #P "," #V "," #R ">", 1, 1}
+#define SC_ALL(P, V)                                                                                \
+  SC_GATHER(P, false, 0), SC_GATHER(P, true, 0), SC_GATHER(P, true, 1), SC_STRIP(P, V, 6), SC_STRIP(P, V, 14)
 
 static const StepKernel kTable[] = {
     GATHER_ALL(P_F64),     GATHER_ALL(P_F32),     GATHER_ALL(P_F16S),    GATHER_ALL(P_BF16S),
@@ -53,6 +63,8 @@ static const StepKernel kTable[] = {
     FUSED_ROWS(P_F16S, 2, 2),  FUSED_ROWS(P_F16S, 4, 2),  FUSED_ROWS(P_BF16S, 2, 2),
     FUSED_ROWS(P_BF16S, 4, 2),
     BGK_ALL(P_F64), BGK_ALL(P_F32), BGK_ALL(P_F16S), BGK_ALL(P_BF16S),
+    SC_ALL(P_F64, 2),  SC_ALL(P_F32, 2),  SC_STRIP(P_F32, 4, 6), SC_STRIP(P_F32, 4, 14),
+    SC_ALL(P_F16S, 2), SC_ALL(P_BF16S, 2),
 };
 
 const StepKernel *step_kernels(int *count) {
@@ -71,6 +83,16 @@ const void *reduce_partial_kernel(int prec) {
 }
 
 const void *reduce_final_kernel() { return (const void *)&k_reduce_final; }
+
+const void *bgk_psi_kernel(int prec) {
+  switch (prec) {
+    case P_F64: return (const void *)&k_bgk_psi<P_F64>;
+    case P_F32: return (const void *)&k_bgk_psi<P_F32>;
+    case P_F16S: return (const void *)&k_bgk_psi<P_F16S>;
+    case P_BF16S: return (const void *)&k_bgk_psi<P_BF16S>;
+  }
+  return nullptr;
+}
 
 const void *bgk_reduce_partial_kernel(int prec) {
   switch (prec) {

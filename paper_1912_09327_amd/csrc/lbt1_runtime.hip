@@ -97,6 +97,11 @@ Layout layout_of(int nx, int ny, int prec, uint32_t options) {
       off += L.state;
     }
   }
+  L.psi_off = 0;
+  if (pop && (options & LBT1_OPT_MULTIPHASE)) {
+    L.psi_off = off;
+    off += round_up((size_t)L.pitch * ny * (prec == LBT1_F64 ? 8 : 4), 256);
+  }
   L.nparts = kReduceBlocks;
   L.part_off = off;
   off += round_up((size_t)L.nparts * 6 * sizeof(double), 256);
@@ -232,12 +237,12 @@ static lbt1_status check_device(int *dev_out, int *cus) {
 // ----------------------------------------------------------------- kernel selection
 static bool strip_fits(int nx, int vec) { return vec >= 1 && nx % vec == 0; }
 
-const StepKernel *find_kernel(int prec, bool haswall, int wall, int kind, int vec, int rows, int fuse) {
+const StepKernel *find_kernel(int prec, bool haswall, int wall, int kind, int vec, int rows, int fuse, bool sc) {
   int n = 0;
   const StepKernel *t = step_kernels(&n);
   for (int i = 0; i < n; ++i) {
     const StepKernel &k = t[i];
-    if (k.prec != prec || k.kind != kind || (k.haswall != 0) != haswall) continue;
+    if (k.prec != prec || k.kind != kind || (k.haswall != 0) != haswall || (k.sc != 0) != sc) continue;
     if (haswall && k.wall != wall) continue;
     if (kind == KIND_STRIP && (k.vec != vec || k.rows != rows || k.steps != fuse)) continue;
     return &k;
@@ -249,7 +254,8 @@ static std::mutex g_tune_mu;
 static std::map<std::tuple<int, int, int, int, int>, lbt1_kernel_config> g_tuned;
 
 static std::tuple<int, int, int, int, int> tune_key(const lbt1_grid *g) {
-  return std::make_tuple(g->prec, (int)g->haswall, g->haswall ? g->wall : 0, g->nx, g->ny);
+  // multiphase grids tune separately (precision code offset by 8)
+  return std::make_tuple(g->prec + (g->mp ? 8 : 0), (int)g->haswall, g->haswall ? g->wall : 0, g->nx, g->ny);
 }
 
 // Default without a tuned entry: the gather kernel for tiny grids, else the
@@ -257,10 +263,21 @@ static std::tuple<int, int, int, int, int> tune_key(const lbt1_grid *g) {
 // wider than the grid, with short strips (6 rows) when tall ones would not give
 // every CU several wavefronts (a strip's rows are walked one after another, so
 // its length sets the latency of a step).
-lbt1_kernel_config heuristic_config(int prec, bool haswall, int wall, int nx, int ny, int cus) {
+lbt1_kernel_config heuristic_config(int prec, bool haswall, int wall, int nx, int ny, int cus, bool sc) {
   lbt1_kernel_config c{};
   if ((long)nx * ny < 64 * 64) {
     c.kernel = LBT1_KERNEL_GATHER;
+    return c;
+  }
+  if (sc) {
+    // multiphase: strips (2 columns per lane) on periodic grids without walls, else gather
+    c.kernel = LBT1_KERNEL_GATHER;
+    if (!haswall && nx % 2 == 0 && find_kernel(prec, false, 0, KIND_STRIP, 2, 14, 1, true)) {
+      c.kernel = LBT1_KERNEL_STRIP;
+      c.vec = 2;
+      c.rows = 14;
+      c.fuse = 1;
+    }
     return c;
   }
   c.kernel = LBT1_KERNEL_STRIP;
@@ -274,7 +291,7 @@ lbt1_kernel_config heuristic_config(int prec, bool haswall, int wall, int nx, in
     if (nx % v == 0 && 62 * v <= std::max(62, nx)) {
       const long tall = (long)((nx / v + 61) / 62) * ((ny + 13) / 14);
       const int r = (prec == LBT1_F16S || prec == LBT1_BF16S) && tall >= 8L * cus ? 14 : 6;
-      if (find_kernel(prec, false, 0, KIND_STRIP, v, r, 2)) {
+      if (find_kernel(prec, false, 0, KIND_STRIP, v, r, 2, false)) {
         c.vec = v;
         c.rows = r;
         c.fuse = 2;
@@ -284,7 +301,7 @@ lbt1_kernel_config heuristic_config(int prec, bool haswall, int wall, int nx, in
   }
   const int cands[] = {8, 4, 2, 1};
   for (int v : cands) {
-    if (nx % v == 0 && 62 * v <= std::max(62, nx) && find_kernel(prec, haswall, wall, KIND_STRIP, v, 14, 1)) {
+    if (nx % v == 0 && 62 * v <= std::max(62, nx) && find_kernel(prec, haswall, wall, KIND_STRIP, v, 14, 1, false)) {
       c.vec = v;
       break;
     }
@@ -298,7 +315,7 @@ lbt1_kernel_config heuristic_config(int prec, bool haswall, int wall, int nx, in
 lbt1_status bind_config(lbt1_grid *g, const lbt1_kernel_config &want, int cus) {
   if (g->pop) {
     // one kernel: a thread per node (the gather launch shape)
-    const StepKernel *k = find_kernel(g->prec, g->haswall, g->wall, KIND_BGK, 0, 0, 1);
+    const StepKernel *k = find_kernel(g->prec, g->haswall, g->wall, KIND_BGK, 0, 0, 1, g->mp);
     if (!k) return fail(LBT1_EINVAL, "no built population kernel at this precision");
     g->kern = g->kern1 = k;
     g->cfg = lbt1_kernel_config{};
@@ -314,11 +331,11 @@ lbt1_status bind_config(lbt1_grid *g, const lbt1_kernel_config &want, int cus) {
   if (c.kernel == LBT1_KERNEL_AUTO) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tuned.find(tune_key(g));
-    c = it != g_tuned.end() ? it->second : heuristic_config(g->prec, g->haswall, g->wall, g->nx, g->ny, cus);
+    c = it != g_tuned.end() ? it->second : heuristic_config(g->prec, g->haswall, g->wall, g->nx, g->ny, cus, g->mp);
   }
   const StepKernel *k = nullptr, *k1 = nullptr;
   if (c.kernel == LBT1_KERNEL_GATHER) {
-    k = k1 = find_kernel(g->prec, g->haswall, g->wall, KIND_GATHER, 0, 0, 1);
+    k = k1 = find_kernel(g->prec, g->haswall, g->wall, KIND_GATHER, 0, 0, 1, g->mp);
     c.vec = c.rows = c.waves = 0;
     c.fuse = 1;
   } else if (c.kernel == LBT1_KERNEL_STRIP) {
@@ -329,8 +346,11 @@ lbt1_status bind_config(lbt1_grid *g, const lbt1_kernel_config &want, int cus) {
     if (c.fuse < 1 || c.fuse > c.vec) return fail(LBT1_EINVAL, "fuse %d must be between 1 and vec %d", c.fuse, c.vec);
     if (c.fuse > 1 && g->haswall)
       return fail(LBT1_EINVAL, "fused steps need a grid periodic in x and y without SOLID or FIXED nodes");
-    k = find_kernel(g->prec, g->haswall, g->wall, KIND_STRIP, c.vec, c.rows, c.fuse);
-    k1 = find_kernel(g->prec, g->haswall, g->wall, KIND_STRIP, c.vec, c.rows, 1);
+    if (c.fuse > 1 && g->mp) return fail(LBT1_EINVAL, "multiphase grids take one step per launch");
+    if (g->mp && g->haswall)
+      return fail(LBT1_EINVAL, "multiphase strips need a grid periodic in x and y without SOLID nodes (use gather)");
+    k = find_kernel(g->prec, g->haswall, g->wall, KIND_STRIP, c.vec, c.rows, c.fuse, g->mp);
+    k1 = find_kernel(g->prec, g->haswall, g->wall, KIND_STRIP, c.vec, c.rows, 1, g->mp);
   } else {
     return fail(LBT1_EINVAL, "unknown kernel family %d", c.kernel);
   }
@@ -386,6 +406,8 @@ StepArgs step_args(const lbt1_grid *g, int src_parity) {
   a.is_d = 1.0 / g->sc[0];
   a.is_j = 1.0 / g->sc[1];
   a.trash = g->base + g->L.trash_off;
+  a.sc_G = g->sc_G;
+  a.sc_rho0 = g->sc_rho0;
   return a;
 }
 
@@ -409,6 +431,12 @@ BgkArgs bgk_args(const lbt1_grid *g, int src_parity) {
   a.tiles_x = (g->nx + 63) / 64;
   a.tiles = a.tiles_x * ((g->ny + 3) / 4);
   a.per_xcd = (a.tiles + 7) / 8;
+  a.psi = g->psi;
+  a.sc_G = g->sc_G;
+  a.sc_rho0 = g->sc_rho0;
+  a.tau = g->tau;
+  a.bfx = g->F[0];
+  a.bfy = g->F[1];
   return a;
 }
 
@@ -418,6 +446,10 @@ hipError_t launch_step(lbt1_grid *g, const StepKernel *k, int src_parity, hipStr
   if (k->kind == KIND_BGK) {
     BgkArgs b = bgk_args(g, src_parity);
     void *args[] = {&b};
+    if (g->mp) {
+      hipError_t e = hipLaunchKernel(bgk_psi_kernel(g->prec), g->grid, g->block, args, 0, s);
+      if (e != hipSuccess) return e;
+    }
     return hipLaunchKernel(k->fn, g->grid, g->block, args, 0, s);
   }
   StepArgs a = step_args(g, src_parity);
@@ -457,6 +489,17 @@ static lbt1_status build_burst(lbt1_grid *g, int p) {
     kp.kernelParams = g->kern->kind == KIND_STRIP ? args_strip : args_gather;
     kp.extra = nullptr;
     hipGraphNode_t node;
+    if (g->pop && g->mp) {
+      // multiphase population grids: the psi pass before each step
+      hipKernelNodeParams pp = kp;
+      pp.func = const_cast<void *>(bgk_psi_kernel(g->prec));
+      e = hipGraphAddKernelNode(&node, graph, prev ? &prev : nullptr, prev ? 1 : 0, &pp);
+      if (e != hipSuccess) {
+        hipGraphDestroy(graph);
+        return hip_fail(e, "hipGraphAddKernelNode");
+      }
+      prev = node;
+    }
     e = hipGraphAddKernelNode(&node, graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
     if (e != hipSuccess) {
       hipGraphDestroy(graph);
@@ -615,7 +658,9 @@ static lbt1_status set_geometry_pop(lbt1_grid *g, const uint8_t *flags, const do
       mom[nx + x] = a;
       mom[2 * nx + x] = b;
       if (fl == LBT1_SOLID) {
-        for (int q = 0; q < 9; ++q) rows[(size_t)q * nx + x] = 0.0;
+        // zero-velocity equilibrium of the given density (never streamed; read by
+        // the multiphase psi pass)
+        for (int q = 0; q < 9; ++q) rows[(size_t)q * nx + x] = kHostW[q] * (r - 1.0);
         continue;
       }
       const double shift = fl == LBT1_FIXED ? g->tau : 0.0;
@@ -697,8 +742,14 @@ lbt1_status lbt1_create_grid(const lbt1_grid_desc *d, lbt1_grid **out) {
   if (!valid_prec(d->prec)) return fail(LBT1_EINVAL, "unknown precision %d", d->prec);
   if (d->wall != LBT1_WALL_PAPER && d->wall != LBT1_WALL_HALFWAY) return fail(LBT1_EINVAL, "unknown wall rule %d", d->wall);
   if (d->periodic & ~3u) return fail(LBT1_EINVAL, "periodic mask %u", d->periodic);
-  if (d->options & ~(uint32_t)(LBT1_OPT_SNAPSHOT | LBT1_OPT_PLANAR | LBT1_OPT_POPULATIONS))
+  if (d->options & ~(uint32_t)(LBT1_OPT_SNAPSHOT | LBT1_OPT_PLANAR | LBT1_OPT_POPULATIONS | LBT1_OPT_MULTIPHASE))
     return fail(LBT1_EINVAL, "unknown options %u", d->options);
+  const bool sc = d->options & LBT1_OPT_MULTIPHASE;
+  const double rho0 = d->sc_rho0 == 0.0 ? 1.0 : d->sc_rho0;
+  if (sc && (!std::isfinite(d->sc_G) || !(rho0 > 0.0) || !std::isfinite(rho0)))
+    return fail(LBT1_EINVAL, "multiphase: sc_G must be finite and sc_rho0 > 0");
+  if (!sc && (d->sc_G != 0.0 || d->sc_rho0 != 0.0))
+    return fail(LBT1_EINVAL, "sc_G / sc_rho0 given without LBT1_OPT_MULTIPHASE");
   const bool pop = d->options & LBT1_OPT_POPULATIONS;
   const double tau = d->tau == 0.0 ? 1.0 : d->tau;
   if (pop && !(tau > 0.5 && std::isfinite(tau))) return fail(LBT1_EINVAL, "tau = %g: must be finite and > 1/2", d->tau);
@@ -721,6 +772,9 @@ lbt1_status lbt1_create_grid(const lbt1_grid_desc *d, lbt1_grid **out) {
   g->options = d->options;
   g->pop = pop;
   g->tau = tau;
+  g->mp = sc;
+  g->sc_G = sc ? d->sc_G : 0.0;
+  g->sc_rho0 = rho0;
   g->F[0] = d->force[0];
   g->F[1] = d->force[1];
   const bool scaled = d->prec == LBT1_F16S || d->prec == LBT1_BF16S;
@@ -764,6 +818,7 @@ lbt1_status lbt1_create_grid(const lbt1_grid_desc *d, lbt1_grid **out) {
   g->flags = (uint8_t *)(g->base + g->L.flags_off);
   for (int q = 0; q < 3; ++q)
     g->snap[q] = (d->options & LBT1_OPT_SNAPSHOT) ? g->base + g->L.snap_off + g->L.snap_field_off[q] : nullptr;
+  g->psi = g->L.psi_off ? g->base + g->L.psi_off : nullptr;
   g->partials = (double *)(g->base + g->L.part_off);
   g->red_out = (double *)(g->base + g->L.out_off);
   if ((e = hipHostMalloc((void **)&g->red_host, 8 * sizeof(double), hipHostMallocDefault)) != hipSuccess) {
@@ -798,6 +853,7 @@ lbt1_status lbt1_set_geometry(lbt1_grid *g, const uint8_t *flags, const double *
     fluid = (int64_t)n;
   }
   if (any_fixed && !rho && !jx && !jy) return fail(LBT1_EINVAL, "FIXED nodes need moments");
+  if (any_fixed && g->mp) return fail(LBT1_EINVAL, "multiphase grids have no FIXED nodes");
   for (size_t i = 0; rho && i < n; ++i)
     if (!(rho[i] > 0.0) || !std::isfinite(rho[i])) return fail(LBT1_EINVAL, "rho[%zu] = %g must be finite and > 0", i, rho[i]);
   for (size_t i = 0; jx && i < n; ++i)
@@ -1074,8 +1130,9 @@ lbt1_status lbt1_autotune(lbt1_grid *g, int32_t steps, int32_t reps, lbt1_kernel
       for (int w : waves)
         for (int f : fuses) {
           if (!strip_fits(g->nx, v)) continue;
-          if (f > 1 && g->haswall) continue;
-          if (!find_kernel(g->prec, g->haswall, g->wall, KIND_STRIP, v, r, f)) continue;
+          if (f > 1 && (g->haswall || g->mp)) continue;
+          if (g->mp && g->haswall) continue;
+          if (!find_kernel(g->prec, g->haswall, g->wall, KIND_STRIP, v, r, f, g->mp)) continue;
           if (64 * v > 2 * std::max(64, g->nx)) continue;
           lbt1_kernel_config c{};
           c.kernel = LBT1_KERNEL_STRIP;

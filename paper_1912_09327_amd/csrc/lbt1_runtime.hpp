@@ -24,6 +24,7 @@ struct Layout {
   size_t snap_off;    // 0 without LBT1_OPT_SNAPSHOT
   int snap_rs;        // row stride of the snapshot's three moment fields
   size_t snap_field_off[3];
+  size_t psi_off;     // multiphase population grids: psi of every node, 0 otherwise
   int nparts;
   size_t part_off, out_off, trash_off;
   size_t total;
@@ -45,6 +46,9 @@ struct lbt1_grid {
   uint32_t options = 0;
   bool pop = false;       // LBT1_OPT_POPULATIONS: stored-population BGK
   double tau = 1.0;
+  bool mp = false;        // LBT1_OPT_MULTIPHASE: Shan-Chen force
+  double sc_G = 0.0, sc_rho0 = 1.0;
+  void *psi = nullptr;    // population grids with sc: psi field
   double F[2] = {0, 0};
   double sc[2] = {1, 1};  // decode scales of d and j
   lbt1::Layout L{};

@@ -38,11 +38,11 @@ class Grid:
 
     ``populations=True`` makes a stored-population BGK grid with relaxation time
     ``tau`` (the standard method, for comparison and tau != 1); by default the
-    grid is LBMTau1."""
+    grid is LBMTau1.  ``multiphase=(G, rho0)`` adds the Shan-Chen force."""
 
     def __init__(self, nx, ny, prec="f32", wall="paper", periodic=0, force=(0.0, 0.0),
                  scale=(0.0, 0.0), snapshot=True, stream=None, torch_memory=True, planar=False,
-                 populations=False, tau=1.0):
+                 populations=False, tau=1.0, multiphase=None):
         import torch
         self.nx, self.ny = int(nx), int(ny)
         self.prec = _prec(prec)
@@ -50,7 +50,8 @@ class Grid:
         self.periodic = int(periodic)
         self.force = (float(force[0]), float(force[1]))
         self.options = ((C.OPT_SNAPSHOT if snapshot else 0) | (C.OPT_PLANAR if planar else 0)
-                        | (C.OPT_POPULATIONS if populations else 0))
+                        | (C.OPT_POPULATIONS if populations else 0)
+                        | (C.OPT_MULTIPHASE if multiphase is not None else 0))
         self.tau = float(tau)
         self.stream = stream if stream is not None else default_stream()
         nbytes = C.grid_bytes(self.nx, self.ny, self.prec, self.options)
@@ -63,6 +64,8 @@ class Grid:
         d.force[0], d.force[1] = self.force
         d.scale[0], d.scale[1] = float(scale[0]), float(scale[1])
         d.tau = self.tau
+        if multiphase is not None:
+            d.sc_G, d.sc_rho0 = float(multiphase[0]), float(multiphase[1])
         self._buf = None
         if torch_memory:
             self._buf = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
