@@ -24,8 +24,10 @@ launch), --workload serve (continuous-batching server vs FIFO), --workload
 compare (LBMTau1 against the stored-population BGK method on the same field:
 the paper's memory comparison measured, and the speed ratio), --workload
 stability (largest stable Reynolds number of the lid-driven cavity against
-grid size at tau = 1, 0.55, 0.7 and 1.5, with the power-law fits); each
-prints its own line.
+grid size at tau = 1, 0.55, 0.7 and 1.5, with the power-law fits), --workload
+drop (the paper's multiphase performance test: a liquid drop in periodic
+vapour, L = 128..8192, multiphase LBMTau1 against the stored-population
+multiphase method); each prints its own line.
 """
 import argparse
 import hashlib
@@ -54,7 +56,7 @@ def parse():
     p.add_argument("--steps", type=int, default=1000)
     p.add_argument("--warmup", type=int, default=100)
     p.add_argument("--workload", default="periodic",
-                   choices=["periodic", "cavities", "serve", "compare", "stability"])
+                   choices=["periodic", "cavities", "serve", "compare", "stability", "drop"])
     p.add_argument("--n", type=int, default=8192, help="grid side of the periodic workload")
     p.add_argument("--storage", default="f32", choices=["f64", "f32", "f16s", "bf16s"])
     p.add_argument("--no-variants", action="store_true", help="skip the other storage variants")
@@ -414,6 +416,66 @@ def run_stability(args, torch):
     }
 
 
+def run_drop(args, torch):
+    """The multiphase drop test of the paper's performance evaluation: a drop of
+    radius L/4 in a periodic L x L box of vapour (Shan-Chen force, G = -5.5), run
+    with multiphase LBMTau1 (no psi field, one kernel per step) and with the
+    stored-population method (nine populations and a psi field, two kernels per
+    step); iterations per second, MLUPS and device bytes per node against L."""
+    from paper_1912_09327_amd import _capi as C
+    from paper_1912_09327_amd.grid import Grid
+    G = (-5.5, 1.0)
+    st = args.storage
+    rows = []
+    for L in (128, 256, 512, 1024, 2048, 4096, 8192):
+        y, x = np.mgrid[0:L, 0:L]
+        d = np.hypot(x - L / 2 + 0.5, y - L / 2 + 0.5)
+        rho = 0.104 + (2.307 - 0.104) * 0.5 * (1 - np.tanh((d - L / 4) / 2))
+        z = np.zeros_like(rho)
+        steps = max(200, min(5000, int(2e11 / (L * L) / 100) * 100))
+        rec = dict(L=L, steps=steps)
+        for name, kw in (("lbmtau1", {}), ("populations", dict(populations=True, tau=1.0))):
+            g = Grid(L, L, prec=st, periodic=3, multiphase=G, **kw)
+            g.set_geometry(None, rho, z, z)
+            if not kw:
+                g.autotune(steps=10, reps=2)
+            wall, kms = timed_run(g, steps, min(100, steps // 4), torch)
+            dd = g.reduce()
+            opts = g.options & ~C.OPT_SNAPSHOT
+            rec[name] = dict(kernel=g.kernel()[1], it_per_s=round(steps / wall, 1),
+                             mlups=round(L * L * steps / wall / 1e6, 1),
+                             device_bytes_per_node=round(C.grid_bytes(L, L, C.PRECISIONS[st], opts) / (L * L), 3),
+                             nonfinite=int(dd["nonfinite"]))
+            g.close()
+            torch.cuda.empty_cache()
+        rec["speed_ratio"] = round(rec["lbmtau1"]["mlups"] / rec["populations"]["mlups"], 2)
+        rec["memory_ratio"] = round(rec["populations"]["device_bytes_per_node"] /
+                                    rec["lbmtau1"]["device_bytes_per_node"], 3)
+        log(f"[drop] L={L}: LBMTau1 {rec['lbmtau1']['mlups']:.0f} MLUPS "
+            f"({rec['lbmtau1']['it_per_s']:.0f} it/s), populations {rec['populations']['mlups']:.0f} MLUPS, "
+            f"speed x{rec['speed_ratio']}, memory x{rec['memory_ratio']}")
+        rows.append(rec)
+    big = rows[-1]
+    return {
+        "metric": METRIC,
+        "value": big["lbmtau1"]["mlups"],
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": big["steps"],
+        "warmup": None,
+        "ms_per_step": round(1e3 / big["lbmtau1"]["it_per_s"], 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if st == "f64" else "f32",
+        "data": "synthetic",
+        "config": {"workload": "multiphase drop test: drop of radius L/4 in periodic vapour, Shan-Chen force "
+                               f"G = -5.5, psi = 1 - exp(-rho), tau = 1, {st} storage, L = 128..8192",
+                   "storage": st},
+        "sizes": rows,
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -427,6 +489,8 @@ def main():
         return 1
     if args.workload == "periodic":
         line = run_periodic(args, torch)
+    elif args.workload == "drop":
+        line = run_drop(args, torch)
     elif args.workload == "stability":
         line = run_stability(args, torch)
     elif args.workload == "compare":

@@ -270,9 +270,11 @@ lbt1_kernel_config heuristic_config(int prec, bool haswall, int wall, int nx, in
     return c;
   }
   if (sc) {
-    // multiphase: strips (2 columns per lane) on periodic grids without walls, else gather
+    // multiphase: strips (2 columns per lane) on periodic grids without walls that
+    // give every CU two strips or more, else one thread per node
     c.kernel = LBT1_KERNEL_GATHER;
-    if (!haswall && nx % 2 == 0 && find_kernel(prec, false, 0, KIND_STRIP, 2, 14, 1, true)) {
+    const long strips = (long)((nx / 2 + 61) / 62) * ((ny + 13) / 14);
+    if (!haswall && nx % 2 == 0 && strips >= 2L * cus && find_kernel(prec, false, 0, KIND_STRIP, 2, 14, 1, true)) {
       c.kernel = LBT1_KERNEL_STRIP;
       c.vec = 2;
       c.rows = 14;
