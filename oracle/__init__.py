@@ -10,6 +10,8 @@ Contents
   FP64, following Algorithm 1 of section 2.1 in the paper's direction order,
   and its multiphase form with the Shan-Chen force of Eq. f_sc
   (``run(..., sc=(G, rho0))``, ``sc_force``).
+* ``lbt1_oracle3d.c`` (wrapped here): the same step on the 3-D lattices of the
+  paper's memory analysis, D3Q19 and D3Q27 (``run3``, ``tables3``).
 * ``bgk``: brute-force stored-population BGK (Eq. lbm) with streaming and
   bounce-back, any tau; at tau = 1 it must agree with the moments-only step
   (Eq. LBMTau1).
@@ -41,8 +43,8 @@ def _load():
     if _lib is not None:
         return _lib
     default = _LIB_PATH == os.path.join(HERE, "liboracle.so")
-    if default and (not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(
-            os.path.join(HERE, "lbt1_oracle.c"))):
+    if default and (not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < max(
+            os.path.getmtime(os.path.join(HERE, f)) for f in ("lbt1_oracle.c", "lbt1_oracle3d.c"))):
         from . import build as _b
         _b.build()
     lib = ctypes.CDLL(_LIB_PATH)
@@ -69,6 +71,13 @@ def _load():
                                     ctypes.c_double, ctypes.c_double, _dp, _dp, _dp]
     lib.oracle_sc_psi.restype = ctypes.c_double
     lib.oracle_sc_psi.argtypes = [ctypes.c_double, ctypes.c_double]
+    lib.oracle3_tables.restype = ctypes.c_int
+    lib.oracle3_tables.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_int), _dp]
+    lib.oracle3_run.restype = ctypes.c_int
+    lib.oracle3_run.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint, _u8p,
+                                ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_long,
+                                _dp, _dp, _dp, _dp]
+    lib.oracle3_set_threads.argtypes = [ctypes.c_int]
     lib.oracle_set_threads.argtypes = [ctypes.c_int]
     lib.oracle_get_threads.restype = ctypes.c_int
     _lib = lib
@@ -126,6 +135,7 @@ def feq(k, r, u, v):
 
 def set_threads(n):
     _load().oracle_set_threads(int(n))
+    _load().oracle3_set_threads(int(n))
 
 
 def get_threads():
@@ -209,3 +219,28 @@ def reduce(rho, jx, jy, flags=None, snapshot=None):
         raise ValueError("oracle_reduce failed")
     return dict(mass=out[0], mom_x=out[1], mom_y=out[2], residual=out[3],
                 nonfinite=int(out[4]), fluid=int(out[5]))
+
+
+def tables3(q):
+    """(e [q, 3], w [q]) of the oracle's D3Q19 or D3Q27 lattice."""
+    e = (ctypes.c_int * 81)()
+    w = (ctypes.c_double * 27)()
+    n = _load().oracle3_tables(int(q), e, w)
+    if n < 0:
+        raise ValueError(q)
+    return np.array(list(e)[:3 * n]).reshape(n, 3), np.array(list(w)[:n])
+
+
+def run3(rho, jx, jy, jz, nsteps, q=19, flags=None, periodic=0, force=(0.0, 0.0, 0.0), wall=WALL_PAPER):
+    """``nsteps`` 3-D LBMTau1 steps on [nz, ny, nx] arrays; returns (rho, jx, jy, jz).
+    periodic: bit 0 x, bit 1 y, bit 2 z."""
+    rho = np.asarray(rho)
+    shape = rho.shape
+    nz, ny, nx = shape
+    st = [np.array(_f64(a, shape), copy=True) for a in (rho, jx, jy, jz)]
+    f = _flags(flags, shape)
+    rc = _load().oracle3_run(int(q), nx, ny, nz, int(periodic), _fptr(f), float(force[0]), float(force[1]),
+                             float(force[2]), int(wall), int(nsteps), *[_ptr(a) for a in st])
+    if rc:
+        raise ValueError(f"oracle3_run failed ({rc})")
+    return tuple(st)

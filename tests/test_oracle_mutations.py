@@ -9,6 +9,7 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "lbt1_oracle.c")
+SRC3 = os.path.join(ROOT, "oracle", "lbt1_oracle3d.c")
 
 MUTATIONS = {
     "dropped_quadratic_term": ("4.5 * eu * eu", "0.0 * eu * eu"),
@@ -30,16 +31,37 @@ MUTATIONS = {
 }
 
 
-@pytest.mark.parametrize("name", sorted(MUTATIONS))
-def test_planted_mistake_fails_a_pin(name, tmp_path):
-    old, new = MUTATIONS[name]
-    text = open(SRC).read()
-    assert text.count(old) == 1, name
-    src = tmp_path / "mutant.c"
-    src.write_text(text.replace(old, new))
+# mistakes in the 3-D oracle
+MUTATIONS3 = {
+    "3d_weight_of_edges": ("{1.0 / 3.0, 1.0 / 18.0, 1.0 / 36.0}", "{1.0 / 3.0, 1.0 / 18.0, 1.0 / 18.0}"),
+    "3d_momentum_z_from_y": ("ws += L.e[d][2] * f;", "ws += L.e[d][1] * f;"),
+    "3d_source_not_upwind": ("long s = nb3(nx, ny, nz, periodic, i, j, k, L.e[id]);",
+                             "long s = nb3(nx, ny, nz, periodic, i, j, k, L.e[d]);"),
+    "3d_z_wrap": ("c = (c + nz) % nz;", "c = (c + ny) % ny;"),
+}
+
+
+def _build(tmp_path, name, which, old, new):
+    srcs = []
+    for path in (SRC, SRC3):
+        text = open(path).read()
+        if path == which:
+            assert text.count(old) == 1, name
+            text = text.replace(old, new)
+        f = tmp_path / os.path.basename(path)
+        f.write_text(text)
+        srcs.append(str(f))
     lib = tmp_path / "libmutant.so"
     subprocess.run(["gcc", "-O1", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-fopenmp",
-                    "-o", str(lib), str(src), "-lm"], check=True)
+                    "-o", str(lib), *srcs, "-lm"], check=True)
+    return lib
+
+
+@pytest.mark.parametrize("name", sorted(MUTATIONS) + sorted(MUTATIONS3))
+def test_planted_mistake_fails_a_pin(name, tmp_path):
+    which = SRC if name in MUTATIONS else SRC3
+    old, new = MUTATIONS.get(name) or MUTATIONS3[name]
+    lib = _build(tmp_path, name, which, old, new)
     env = dict(os.environ, LBT1_ORACLE_LIB=str(lib))
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                         os.path.join(ROOT, "tests", "test_oracle_pins.py")],
@@ -48,9 +70,7 @@ def test_planted_mistake_fails_a_pin(name, tmp_path):
 
 
 def test_control_unmodified_copy_passes(tmp_path):
-    lib = tmp_path / "libcopy.so"
-    subprocess.run(["gcc", "-O1", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-fopenmp",
-                    "-o", str(lib), SRC, "-lm"], check=True)
+    lib = _build(tmp_path, "control", None, "", "")
     env = dict(os.environ, LBT1_ORACLE_LIB=str(lib))
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                         os.path.join(ROOT, "tests", "test_oracle_pins.py")],

@@ -587,3 +587,113 @@ def test_p11_laplace_law():
         sig.append((p(r[L // 2, L // 2]) - p(r[0, 0])) * radius)
     assert max(sig) / min(sig) - 1 < 0.02, sig
     assert 0.08 < np.mean(sig) < 0.11
+
+
+# ----------------------------------------------------------------- P12 3-D lattices
+from oracle import bgk3  # noqa: E402
+
+
+@pytest.mark.parametrize("q", [19, 27])
+def test_p12_3d_lattice_is_isotropic(q):
+    """Section 4's D3Q19 / D3Q27: weights sum to 1, first and third moments vanish,
+    sum w e_a e_b = delta_ab / 3 and the fourth moment is isotropic (1/9 of the
+    symmetrised delta product): exact rational arithmetic."""
+    e, w = oracle.tables3(q)
+    assert len(e) == q
+    W = [Fraction(x).limit_denominator(1000) for x in w]
+    assert sum(W) == 1
+    for a in range(3):
+        assert sum(Wk * ek[a] for Wk, ek in zip(W, e)) == 0
+        for b in range(3):
+            assert sum(Wk * ek[a] * ek[b] for Wk, ek in zip(W, e)) == (Fraction(1, 3) if a == b else 0)
+            for c in range(3):
+                assert sum(Wk * ek[a] * ek[b] * ek[c] for Wk, ek in zip(W, e)) == 0
+                for d in range(3):
+                    iso = Fraction(1, 9) * ((a == b) * (c == d) + (a == c) * (b == d) + (a == d) * (b == c))
+                    assert sum(Wk * ek[a] * ek[b] * ek[c] * ek[d] for Wk, ek in zip(W, e)) == iso
+    inv = {tuple(x) for x in e}
+    assert all(tuple(-x) in inv for x in e)
+
+
+@pytest.mark.parametrize("q", [19, 27])
+@pytest.mark.parametrize("wall", [oracle.WALL_PAPER, oracle.WALL_HALFWAY])
+def test_p12_3d_collapses_to_2d(q, wall):
+    """One periodic layer in z with no z-momentum: the populations with e_z != 0 come
+    back to the same layer and the weights grouped over e_z are those of D2Q9 (4/9,
+    1/9, 1/36), so the 3-D step is the (pinned) 2-D step, walls included."""
+    rng = _rng(120 + q)
+    ny, nx = 9, 11
+    rho, jx, jy = _random_state(rng, ny, nx)
+    flags = (rng.random((ny, nx)) < 0.15).astype(np.uint8)
+    flags[-1, 2:6] = oracle.FIXED
+    F = (1e-4, -3e-5)
+    ref = oracle.run(rho, jx, jy, 20, flags, 1, F, wall)
+    got = oracle.run3(rho[None], jx[None], jy[None], np.zeros((1, ny, nx)), 20, q, flags[None], 1 | 4,
+                      (F[0], F[1], 0.0), wall)
+    for a, b in zip(got[:3], ref):
+        assert np.abs(a[0] - b).max() < 5e-15
+    assert np.abs(got[3]).max() < 1e-16
+
+
+@pytest.mark.parametrize("q", [19, 27])
+@pytest.mark.parametrize("periodic", [0, 7])
+def test_p12_3d_brute_force_bgk_at_tau1(q, periodic):
+    """Eq. lbm vs Eq. LBMTau1 in 3-D: the loop-form stored-population solver at tau = 1
+    and the moments-only 3-D oracle agree to rounding (walls, obstacles, a fixed
+    plane, force, all three momentum components)."""
+    rng = _rng(130 + q + periodic)
+    nz, ny, nx = 4, 5, 6
+    shape = (nz, ny, nx)
+    rho = 1.0 + 1e-2 * rng.standard_normal(shape)
+    js = [rho * 1e-2 * rng.standard_normal(shape) for _ in range(3)]
+    flags = (rng.random(shape) < 0.12).astype(np.uint8)
+    flags[-1, 1:4, 1:4] = oracle.FIXED
+    F = (1e-4, -2e-5, 3e-5)
+    for wall in (oracle.WALL_PAPER, oracle.WALL_HALFWAY):
+        ref = bgk3.BGK3(q, rho, *js, flags, periodic, F, wall, 1.0).run(6)
+        got = oracle.run3(rho, *js, 6, q, flags, periodic, F, wall)
+        fl = flags == oracle.FLUID
+        for a, b in zip(got, ref):
+            assert np.abs(a - b)[fl].max() < 5e-15
+
+
+@pytest.mark.parametrize("q", [19, 27])
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_p12_3d_shear_wave_exact(q, axis):
+    """A shear wave along each axis decays exactly by (2 + cos k)/3 per step: the
+    weights grouped by the wave-direction component are 2/3, 1/6, 1/6 on both
+    lattices."""
+    n, m, steps, A = 16, 2, 30, 3e-3
+    k = 2 * np.pi * m / n
+    shape = (n, n, n)
+    coord = np.indices(shape)[2 - axis]          # position along the wave axis (x = index 2)
+    rho = np.ones(shape)
+    js = [np.zeros(shape) for _ in range(3)]
+    js[(axis + 1) % 3] = A * np.sin(k * coord)   # momentum transverse to the wave
+    got = oracle.run3(rho, *js, steps, q, None, 7)
+    lam = cf.shear_wave_factor(k)
+    assert np.abs(got[1 + (axis + 1) % 3] - A * lam ** steps * np.sin(k * coord)).max() < 1e-15
+    assert np.abs(got[0] - 1).max() <= 8 * EPS * steps     # weights sum to 1 up to rounding
+
+
+@pytest.mark.parametrize("q", [19, 27])
+def test_p12_3d_plate_channel_and_conservation(q):
+    """Plates at z = 0 and z = nz - 1, force along x: x- and y-invariant flow follows
+    the exact 1-D channel recurrence of the 2-D channel (same grouped weights);
+    periodic mass and momentum + n N F are conserved."""
+    nz, F = 12, 1e-5
+    flags = np.zeros((nz, 3, 3), np.uint8)
+    flags[0] = flags[-1] = oracle.SOLID
+    one, zero = np.ones((nz, 3, 3)), np.zeros((nz, 3, 3))
+    got = oracle.run3(one, zero, zero, zero, 400, q, flags, 3, (F, 0.0, 0.0), oracle.WALL_PAPER)
+    ref = cf.channel_1d(nz, F, 0, 400)
+    assert np.abs(got[1][1:-1, 1, 1] - ref[1:-1]).max() < 1e-15
+    rng = _rng(150)
+    shape = (5, 6, 7)
+    rho = 1.0 + 1e-2 * rng.standard_normal(shape)
+    js = [1e-2 * rng.standard_normal(shape) for _ in range(3)]
+    Fv = (2e-5, -1e-5, 3e-5)
+    r = oracle.run3(rho, *js, 25, q, None, 7, Fv)
+    assert abs(r[0].sum() - rho.sum()) <= 8 * EPS * 25 * rho.sum()
+    for a in range(3):
+        assert r[1 + a].sum() == pytest.approx(js[a].sum() + 25 * rho.size * Fv[a], abs=1e-13)
