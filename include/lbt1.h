@@ -249,6 +249,51 @@ lbt1_status lbt1_get_kernel(lbt1_grid *g, lbt1_kernel_config *cfg, char *name, s
 lbt1_status lbt1_autotune(lbt1_grid *g, int32_t steps, int32_t reps, lbt1_kernel_config *best,
                           double *ms_per_step);
 
+/* ---------------------------------------------------------------- 3-D grids */
+
+/* Three-dimensional LBMTau1 on the D3Q19 or D3Q27 lattice (the lattices of the
+ * memory analysis of section 4): the step of Algorithm 1 with Q directions; a
+ * node keeps rho - 1 and (jx, jy, jz), 2 * 4 * c bytes per node over both
+ * parities against (2 Q + 4) c for the standard method (Eq. lbmmemory).  The
+ * body force, the two wall rules and FIXED nodes as in 2-D; a neighbour
+ * outside a non-periodic axis is a wall.  Host arrays are [nz][ny][nx], x
+ * fastest.  Same conventions as the 2-D calls. */
+typedef struct lbt1_grid3d lbt1_grid3d;
+
+typedef struct {
+  int32_t nx, ny, nz;    /* x, y: 3..16384; z: 1..16384 */
+  int32_t q;             /* 19 or 27 */
+  uint32_t periodic;     /* bit 0 x, bit 1 y, bit 2 z */
+  int32_t prec;          /* lbt1_precision */
+  int32_t wall;          /* lbt1_wall */
+  uint32_t options;      /* LBT1_OPT_SNAPSHOT only */
+  double force[3];       /* uniform body force, added to the momentum before the
+                            equilibrium velocity is formed */
+  double scale[2];       /* F16S/BF16S scales of rho - 1 and j (powers of two; 0 = 1) */
+  void *device_buffer;   /* optional caller memory of lbt1_grid3d_bytes(...) bytes, 256-aligned */
+  size_t device_bytes;
+  void *stream;          /* hipStream_t, NULL: a library stream */
+} lbt1_grid3d_desc;
+
+/* Device bytes: two parities of the four moment fields ([nz][ny][4][pitch],
+ * pitch = nx rounded up to 64), one flag byte per node, a snapshot with
+ * LBT1_OPT_SNAPSHOT, reduction workspace.  0 on bad arguments. */
+size_t lbt1_grid3d_bytes(int32_t nx, int32_t ny, int32_t nz, int32_t q, int32_t prec, uint32_t options);
+lbt1_status lbt1_grid3d_create(const lbt1_grid3d_desc *d, lbt1_grid3d **out);
+/* Flags (NULL: all FLUID) and moments (NULL: rho = 1, j = 0); validation as 2-D. */
+lbt1_status lbt1_grid3d_set_geometry(lbt1_grid3d *g, const uint8_t *flags, const double *rho, const double *jx,
+                                     const double *jy, const double *jz);
+/* n steps, asynchronous (one launch per step, one thread per node). */
+lbt1_status lbt1_grid3d_step(lbt1_grid3d *g, int64_t n);
+/* rho and momentum into nz*ny*nx host arrays (any may be NULL); synchronises. */
+lbt1_status lbt1_grid3d_read_moments(lbt1_grid3d *g, double *rho, double *jx, double *jy, double *jz);
+/* FP64 diagnostics over FLUID nodes into out[8]: 0 mass, 1..3 momentum,
+ * 4 residual max |u - u_snap| (LBT1_REDUCE_RESIDUAL, refreshes the snapshot),
+ * 5 non-finite count, 6 FLUID count, 7 zero.  Synchronises. */
+lbt1_status lbt1_grid3d_reduce(lbt1_grid3d *g, uint32_t what, double *out);
+lbt1_status lbt1_grid3d_sync(lbt1_grid3d *g);
+lbt1_status lbt1_grid3d_destroy(lbt1_grid3d *g);
+
 /* ---------------------------------------------------------------- batches */
 
 /* A batch steps every resident grid together: one launch per time step covers

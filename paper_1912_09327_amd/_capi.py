@@ -61,6 +61,15 @@ class KernelConfig(ctypes.Structure):
         return dict(kernel=self.kernel, vec=self.vec, rows=self.rows, waves=self.waves, fuse=self.fuse)
 
 
+class Grid3DDesc(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32), ("q", ctypes.c_int32),
+        ("periodic", ctypes.c_uint32), ("prec", ctypes.c_int32), ("wall", ctypes.c_int32),
+        ("options", ctypes.c_uint32), ("force", ctypes.c_double * 3), ("scale", ctypes.c_double * 2),
+        ("device_buffer", ctypes.c_void_p), ("device_bytes", ctypes.c_size_t), ("stream", ctypes.c_void_p),
+    ]
+
+
 _vp = ctypes.c_void_p
 _dp = ctypes.POINTER(ctypes.c_double)
 _u8p = ctypes.POINTER(ctypes.c_uint8)
@@ -90,6 +99,14 @@ SIGNATURES = {
     "lbt1_batch_evict": (ctypes.c_int, [_vp, _i32]),
     "lbt1_batch_destroy": (ctypes.c_int, [_vp]),
     "lbt1_probe_bandwidth": (ctypes.c_int, [_i32, ctypes.c_size_t, _i32, _i32, _dp]),
+    "lbt1_grid3d_bytes": (ctypes.c_size_t, [_i32, _i32, _i32, _i32, _i32, ctypes.c_uint32]),
+    "lbt1_grid3d_create": (ctypes.c_int, [ctypes.POINTER(Grid3DDesc), ctypes.POINTER(_vp)]),
+    "lbt1_grid3d_set_geometry": (ctypes.c_int, [_vp, _u8p, _dp, _dp, _dp, _dp]),
+    "lbt1_grid3d_step": (ctypes.c_int, [_vp, ctypes.c_int64]),
+    "lbt1_grid3d_read_moments": (ctypes.c_int, [_vp, _dp, _dp, _dp, _dp]),
+    "lbt1_grid3d_reduce": (ctypes.c_int, [_vp, ctypes.c_uint32, _dp]),
+    "lbt1_grid3d_sync": (ctypes.c_int, [_vp]),
+    "lbt1_grid3d_destroy": (ctypes.c_int, [_vp]),
 }
 
 

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbt1.so")
-SOURCES = ["lbt1_kernels.hip", "lbt1_runtime.hip", "lbt1_batch.hip", "lbt1_probe.hip"]
+SOURCES = ["lbt1_kernels.hip", "lbt1_runtime.hip", "lbt1_batch.hip", "lbt1_probe.hip", "lbt1_3d.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

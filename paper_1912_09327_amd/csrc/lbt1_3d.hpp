@@ -1,0 +1,226 @@
+// Three-dimensional LBMTau1 step (D3Q19, D3Q27) for gfx950.
+//
+// The method of section 2 / Algorithm 1 on the 3-D lattices of the memory
+// analysis of section 4: a node keeps its density and momentum (four values,
+// 2 * 4 * c bytes per node over both parities against (2 Q + 4) c for the
+// standard method), and its new moments are the sums over the Q directions of
+// the equilibrium that the upwind node x - e_q sends along e_q.  Walls, lid
+// (FIXED) nodes and the body force as in 2-D.
+//
+// Arithmetic as the 2-D kernels: density as d = rho - 1, equilibrium
+// deviations w_q [d + 3 e.J + 4.5 (e.J)^2 / rho - 1.5 |J|^2 / rho] with the
+// forced momentum J = j + F.  Direction order here: rest, the six faces, the
+// twelve edges, the eight corners (D3Q19 = the first 19).
+#pragma once
+#include "lbt1_device.hpp"
+
+namespace lbt1 {
+
+__device__ constexpr int k3x[27] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0,
+                                    1, -1, 1, -1, 1, -1, 1, -1};
+__device__ constexpr int k3y[27] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1,
+                                    1, -1, 1, -1, -1, 1, -1, 1};
+__device__ constexpr int k3z[27] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1,
+                                    1, -1, -1, 1, 1, -1, -1, 1};
+
+template <int Q>
+__device__ __forceinline__ double w3(int q) {
+  // weight by |e|^2: rest, face, edge, corner
+  const int m = k3x[q] * k3x[q] + k3y[q] * k3y[q] + k3z[q] * k3z[q];
+  if (Q == 19) return m == 0 ? 1.0 / 3.0 : m == 1 ? 1.0 / 18.0 : 1.0 / 36.0;
+  return m == 0 ? 8.0 / 27.0 : m == 1 ? 2.0 / 27.0 : m == 2 ? 1.0 / 54.0 : 1.0 / 216.0;
+}
+
+template <int Q>
+__device__ __forceinline__ int inv3(int q) {
+  return q == 0 ? 0 : ((q - 1) ^ 1) + 1;  // the order pairs e and -e as neighbours
+}
+
+struct Step3Args {
+  const void *src[4];  // d, jx, jy, jz of the current parity
+  void *dst[4];
+  const uint8_t *flags;  // NULL: every node FLUID and all three axes periodic
+  int nx, ny, nz;
+  int pitch;             // values per row of one field (nx rounded up to 64)
+  long rs, zs;           // row and plane strides of the moment fields, in values
+  long fzs;              // plane stride of the flags
+  uint32_t periodic;     // bit 0 x, bit 1 y, bit 2 z
+  double fx, fy, fz;
+  double sc_d, sc_j, is_d, is_j;
+};
+
+// c + e * v for a lattice component e in {-1, 0, 1} (no multiplication; q is
+// known at compile time once the direction loops are unrolled)
+template <typename C>
+__device__ __forceinline__ C add_comp(C c, int e, C v) {
+  return e == 1 ? c + v : e == -1 ? c - v : c;
+}
+
+// Equilibrium deviation a node with deviation d and forced momentum J sends
+// along e_q (inv = 1 / (1 + d), t = |J|^2 inv).
+template <typename C, int Q>
+__device__ __forceinline__ C emit3(int q, C d, C Jx, C Jy, C Jz, C inv, C t) {
+  const C eJ = add_comp<C>(add_comp<C>(add_comp<C>(C(0), k3x[q], Jx), k3y[q], Jy), k3z[q], Jz);
+  const C b = fmaC<C>(C(-1.5), t, d);
+  return C(w3<Q>(q)) * fmaC<C>(C(4.5) * inv, eJ * eJ, fmaC<C>(C(3), eJ, b));
+}
+
+template <int P>
+__device__ __forceinline__ void load3(const Step3Args &a, long i, typename Traits<P>::C &d, typename Traits<P>::C &jx,
+                                      typename Traits<P>::C &jy, typename Traits<P>::C &jz) {
+  using T = Traits<P>;
+  using S = typename T::S;
+  using C = typename T::C;
+  d = T::dec(static_cast<const S *>(a.src[0])[i]);
+  jx = T::dec(static_cast<const S *>(a.src[1])[i]);
+  jy = T::dec(static_cast<const S *>(a.src[2])[i]);
+  jz = T::dec(static_cast<const S *>(a.src[3])[i]);
+  if (T::kScaled) {
+    d *= C(a.sc_d);
+    jx *= C(a.sc_j);
+    jy *= C(a.sc_j);
+    jz *= C(a.sc_j);
+  }
+}
+
+// One thread per node; blocks of 64 x 4 nodes in (x, y), grid (x tiles,
+// y tiles, nz).
+template <int P, int Q, bool HASWALL, int WALL>
+__global__ void __launch_bounds__(256) k_step3_gather(Step3Args a) {
+  using T = Traits<P>;
+  using C = typename T::C;
+  using S = typename T::S;
+  const int x = blockIdx.x * 64 + threadIdx.x;
+  const int y = blockIdx.y * 4 + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x >= a.nx || y >= a.ny) return;
+  const long i = (long)z * a.zs + (long)y * a.rs + x;
+  if (HASWALL && a.flags[(long)z * a.fzs + (long)y * a.pitch + x] != NODE_FLUID) return;  // held
+  const C Fx = C(a.fx), Fy = C(a.fy), Fz = C(a.fz);
+  C d0, jx0, jy0, jz0;
+  load3<P>(a, i, d0, jx0, jy0, jz0);
+  C own_inv = C(0), own_t = C(0);
+  if (HASWALL && WALL == WALL_HALFWAY) {
+    own_inv = recip<C>(C(1) + d0);
+    const C Jx = jx0 + Fx, Jy = jy0 + Fy, Jz = jz0 + Fz;
+    own_t = (Jx * Jx + Jy * Jy + Jz * Jz) * own_inv;
+  }
+  C dn = C(0), xn = C(0), yn = C(0), zn = C(0);
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int sx = wrap_axis(x - k3x[q], a.nx, a.periodic & 1u);
+    const int sy = wrap_axis(y - k3y[q], a.ny, a.periodic & 2u);
+    const int sz = wrap_axis(z - k3z[q], a.nz, a.periodic & 4u);
+    bool solid = sx < 0 || sy < 0 || sz < 0;
+    if (HASWALL && !solid) solid = a.flags[(long)sz * a.fzs + (long)sy * a.pitch + sx] == NODE_SOLID;
+    C f;
+    if (!solid) {
+      C d, jx, jy, jz;
+      load3<P>(a, (long)sz * a.zs + (long)sy * a.rs + sx, d, jx, jy, jz);
+      const C inv = recip<C>(C(1) + d);
+      const C Jx = jx + Fx, Jy = jy + Fy, Jz = jz + Fz;
+      const C t = (Jx * Jx + Jy * Jy + Jz * Jz) * inv;
+      f = emit3<C, Q>(q, d, Jx, Jy, Jz, inv, t);
+    } else if (WALL == WALL_PAPER) {
+      f = C(w3<Q>(q)) * d0;
+    } else {
+      f = emit3<C, Q>(inv3<Q>(q), d0, jx0 + Fx, jy0 + Fy, jz0 + Fz, own_inv, own_t);
+    }
+    dn += f;
+    xn = add_comp<C>(xn, k3x[q], f);
+    yn = add_comp<C>(yn, k3y[q], f);
+    zn = add_comp<C>(zn, k3z[q], f);
+  }
+  if (T::kScaled) {
+    dn *= C(a.is_d);
+    xn *= C(a.is_j);
+    yn *= C(a.is_j);
+    zn *= C(a.is_j);
+  }
+  static_cast<S *>(a.dst[0])[i] = T::enc(dn);
+  static_cast<S *>(a.dst[1])[i] = T::enc(xn);
+  static_cast<S *>(a.dst[2])[i] = T::enc(yn);
+  static_cast<S *>(a.dst[3])[i] = T::enc(zn);
+}
+
+struct Reduce3Args {
+  const void *cur[4];
+  void *snap[4];
+  const uint8_t *flags;
+  int nx, ny, nz, pitch;
+  long rs, zs, fzs;
+  double sc_d, sc_j;
+  uint32_t what;
+  double *partials;  // 8 per block
+};
+
+// out slots: 0 sum d, 1..3 sum j, 4 max residual, 5 non-finite, 6 FLUID count
+template <int P>
+__global__ void __launch_bounds__(256) k_reduce3_partial(Reduce3Args a) {
+  using T = Traits<P>;
+  using S = typename T::S;
+  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  const long n = (long)a.nx * a.ny * a.nz;
+  const bool want_res = a.what & 4u;
+  for (long k = (long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x) {
+    const int x = (int)(k % a.nx);
+    const long yz = k / a.nx;
+    const int y = (int)(yz % a.ny);
+    const int z = (int)(yz / a.ny);
+    if (a.flags && a.flags[(long)z * a.fzs + (long)y * a.pitch + x] != NODE_FLUID) continue;
+    const long i = (long)z * a.zs + (long)y * a.rs + x;
+    double v[4];
+    S r[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      r[m] = static_cast<const S *>(a.cur[m])[i];
+      v[m] = (double)T::dec(r[m]) * (m == 0 ? a.sc_d : a.sc_j);
+    }
+    for (int m = 0; m < 4; ++m) acc[m] += v[m];
+    const bool fin = __builtin_isfinite(v[0]) && __builtin_isfinite(v[1]) && __builtin_isfinite(v[2]) &&
+                     __builtin_isfinite(v[3]);
+    acc[5] += fin ? 0.0 : 1.0;
+    acc[6] += 1.0;
+    if (want_res) {
+      const double rho = 1.0 + v[0];
+      const double sr = 1.0 + (double)T::dec(static_cast<S *>(a.snap[0])[i]) * a.sc_d;
+      double res = 0.0;
+      for (int m = 1; m < 4; ++m) {
+        const double su = (double)T::dec(static_cast<S *>(a.snap[m])[i]) * a.sc_j / sr;
+        res = __builtin_fmax(res, __builtin_fabs(v[m] / rho - su));
+      }
+      acc[4] = __builtin_fmax(acc[4], res);
+      for (int m = 0; m < 4; ++m) static_cast<S *>(a.snap[m])[i] = r[m];
+    }
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      const double o = __shfl_xor(acc[m], off);
+      acc[m] = m == 4 ? __builtin_fmax(acc[m], o) : acc[m] + o;
+    }
+  }
+  __shared__ double part[4][8];
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0)
+    for (int m = 0; m < 8; ++m) part[wave][m] = acc[m];
+  __syncthreads();
+  if (threadIdx.x < 8) {
+    const int m = threadIdx.x;
+    double v = part[0][m];
+    for (int w = 1; w < 4; ++w) v = m == 4 ? __builtin_fmax(v, part[w][m]) : v + part[w][m];
+    a.partials[blockIdx.x * 8 + m] = v;
+  }
+}
+
+__global__ void __launch_bounds__(64) k_reduce3_final(const double *partials, int nparts, double *out) {
+  const int m = threadIdx.x;
+  if (m < 8) {
+    double v = 0.0;
+    for (int b = 0; b < nparts; ++b) v = m == 4 ? __builtin_fmax(v, partials[b * 8 + m]) : v + partials[b * 8 + m];
+    out[m] = v;
+  }
+}
+
+}  // namespace lbt1

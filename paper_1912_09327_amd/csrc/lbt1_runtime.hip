@@ -218,7 +218,7 @@ void decode_values(int prec, const void *in, size_t n, double scale, double *out
 }
 
 // ----------------------------------------------------------------- device check
-static lbt1_status check_device(int *dev_out, int *cus) {
+lbt1_status check_device(int *dev_out, int *cus) {
   int ndev = 0;
   hipError_t e = hipGetDeviceCount(&ndev);
   if (e != hipSuccess) return fail(LBT1_EDEVICE, "no HIP device is visible: hipGetDeviceCount: %s (%d)", hipGetErrorString(e), (int)e);

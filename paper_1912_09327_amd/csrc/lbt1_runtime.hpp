@@ -33,6 +33,9 @@ struct Layout {
 Layout layout_of(int nx, int ny, int prec, uint32_t options);
 size_t value_bytes(int prec);
 lbt1_status fail(lbt1_status st, const char *fmt, ...);
+lbt1_status check_device(int *dev_out, int *cus);
+void encode_values(int prec, const double *in, size_t n, double inv_scale, void *out);
+void decode_values(int prec, const void *in, size_t n, double scale, double *out);
 lbt1_status hip_fail(hipError_t e, const char *what);
 void clear_error();
 

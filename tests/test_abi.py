@@ -65,6 +65,22 @@ def test_grid_bytes_of_population_grids():
     assert 2.9 < ratio < 3.0
 
 
+def test_grid3d_bytes():
+    """3-D: two parities of four moment fields, 2 * 4 * c bytes per node (section 4's
+    LBMTau1 memory with N_f = 4), on padded rows, plus flags."""
+    from paper_1912_09327_amd import _capi as C
+    for prec, c in ((C.F64, 8), (C.F32, 4), (C.F16S, 2)):
+        for nx, ny, nz in ((64, 32, 16), (100, 37, 5)):
+            pitch = (nx + 63) // 64 * 64
+            state = -(-4 * pitch * ny * nz * c // 256) * 256
+            flags = -(-pitch * ny * nz // 256) * 256
+            for q in (19, 27):
+                b = C.lib.lbt1_grid3d_bytes(nx, ny, nz, q, prec, 0)
+                assert 0 <= b - (2 * state + flags) <= 72 * 1024      # reduction workspace only
+                assert C.lib.lbt1_grid3d_bytes(nx, ny, nz, q, prec, C.OPT_SNAPSHOT) == b + state
+    assert C.lib.lbt1_grid3d_bytes(16, 16, 16, 15, C.F32, 0) == 0
+
+
 def test_tau_is_checked():
     from paper_1912_09327_amd import _capi as C
     d = C.GridDesc()
