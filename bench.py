@@ -27,7 +27,8 @@ stability (largest stable Reynolds number of the lid-driven cavity against
 grid size at tau = 1, 0.55, 0.7 and 1.5, with the power-law fits), --workload
 drop (the paper's multiphase performance test: a liquid drop in periodic
 vapour, L = 128..8192, multiphase LBMTau1 against the stored-population
-multiphase method); each prints its own line.
+multiphase method), --workload 3d (3-D LBMTau1 on D3Q19 / D3Q27 periodic
+random fields of 256^3 and 512^3); each prints its own line.
 """
 import argparse
 import hashlib
@@ -56,7 +57,7 @@ def parse():
     p.add_argument("--steps", type=int, default=1000)
     p.add_argument("--warmup", type=int, default=100)
     p.add_argument("--workload", default="periodic",
-                   choices=["periodic", "cavities", "serve", "compare", "stability", "drop"])
+                   choices=["periodic", "cavities", "serve", "compare", "stability", "drop", "3d"])
     p.add_argument("--n", type=int, default=8192, help="grid side of the periodic workload")
     p.add_argument("--storage", default="f32", choices=["f64", "f32", "f16s", "bf16s"])
     p.add_argument("--no-variants", action="store_true", help="skip the other storage variants")
@@ -476,6 +477,73 @@ def run_drop(args, torch):
     }
 
 
+def run_3d(args, torch):
+    """3-D LBMTau1 on periodic random fields (rho = 1 + 1e-3 N(0,1), u = 0.01 N(0,1),
+    seed 0): MLUPS and algorithmic GB/s (2 * 4 * c bytes per LUP) for D3Q19 and D3Q27,
+    with device bytes per node against the standard method's (2 Q + 4) c."""
+    from paper_1912_09327_amd import _capi as C
+    from paper_1912_09327_amd.grid3d import Grid3D
+    st = args.storage
+    c = VALUE_BYTES[st]
+    rows = []
+    for n in (256, 512):
+        g0 = np.random.default_rng(0).standard_normal((4, n, n, n), dtype=np.float32)
+        rho = 1.0 + 1e-3 * g0[0].astype(np.float64)
+        js = [rho * (0.01 * g0[k].astype(np.float64)) for k in (1, 2, 3)]
+        del g0
+        for q in (19, 27):
+            g = Grid3D(n, n, n, q=q, prec=st, periodic=7)
+            g.set_geometry(None, rho, *js)
+            steps = 200 if n == 256 else 50
+            g.step(10)
+            g.sync()
+            s = g.stream
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            a.record(s)
+            g.step(steps)
+            b.record(s)
+            d = g.reduce()
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            kms = a.elapsed_time(b) / steps
+            lups = float(n) ** 3
+            rec = dict(n=n, q=q, steps=steps, mlups=round(lups * steps / wall / 1e6, 1), kernel_ms=round(kms, 4),
+                       achieved_GBps=round(2 * 4 * c * lups / (kms * 1e-3) / 1e9, 1),
+                       device_bytes_per_node=round(C.lib.lbt1_grid3d_bytes(n, n, n, q, C.PRECISIONS[st], 0) / lups, 3),
+                       standard_bytes_per_node=(2 * q + 4) * c, nonfinite=int(d["nonfinite"]))
+            rec["memory_saving"] = round(1 - rec["device_bytes_per_node"] / rec["standard_bytes_per_node"], 4)
+            log(f"[3d] {n}^3 D3Q{q}: {rec['mlups']:.0f} MLUPS, {rec['achieved_GBps']:.0f} GB/s, "
+                f"{rec['device_bytes_per_node']:.1f} vs {rec['standard_bytes_per_node']} B/node")
+            rows.append(rec)
+            g.close()
+            torch.cuda.empty_cache()
+        del rho, js
+    head = [r for r in rows if r["n"] == 512 and r["q"] == 19][0]
+    return {
+        "metric": METRIC,
+        "value": head["mlups"],
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": head["steps"],
+        "warmup": 10,
+        "ms_per_step": head["kernel_ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if st == "f64" else "f32",
+        "data": "synthetic",
+        "config": {"workload": f"3-D LBMTau1, periodic random field (seed 0), {st} storage, 256^3 and 512^3, "
+                               "D3Q19 and D3Q27", "storage": st},
+        "roofline": {"bound": "hbm", "achieved": head["achieved_GBps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": round(head["achieved_GBps"] / HBM_PEAK_GBPS, 4), "traffic": None,
+                     "bytes_per_lup": 2 * 4 * c},
+        "runs": rows,
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -489,6 +557,8 @@ def main():
         return 1
     if args.workload == "periodic":
         line = run_periodic(args, torch)
+    elif args.workload == "3d":
+        line = run_3d(args, torch)
     elif args.workload == "drop":
         line = run_drop(args, torch)
     elif args.workload == "stability":

@@ -291,6 +291,14 @@ lbt1_status lbt1_grid3d_read_moments(lbt1_grid3d *g, double *rho, double *jx, do
  * 4 residual max |u - u_snap| (LBT1_REDUCE_RESIDUAL, refreshes the snapshot),
  * 5 non-finite count, 6 FLUID count, 7 zero.  Synchronises. */
 lbt1_status lbt1_grid3d_reduce(lbt1_grid3d *g, uint32_t what, double *out);
+/* Kernel family: LBT1_KERNEL_AUTO (default) and LBT1_KERNEL_STRIP take the tile
+ * kernel (a 64 x 4 block marches along z with three planes of per-node values
+ * in LDS) on grids periodic in x, y, z without SOLID or FIXED nodes (STRIP:
+ * EINVAL elsewhere); LBT1_KERNEL_GATHER one thread per node.  The two give
+ * the same bits.  get_kernel reports the family bound (ESTATE before
+ * set_geometry). */
+lbt1_status lbt1_grid3d_set_kernel(lbt1_grid3d *g, int32_t kernel);
+lbt1_status lbt1_grid3d_get_kernel(lbt1_grid3d *g, int32_t *kernel);
 lbt1_status lbt1_grid3d_sync(lbt1_grid3d *g);
 lbt1_status lbt1_grid3d_destroy(lbt1_grid3d *g);
 

@@ -105,6 +105,8 @@ SIGNATURES = {
     "lbt1_grid3d_step": (ctypes.c_int, [_vp, ctypes.c_int64]),
     "lbt1_grid3d_read_moments": (ctypes.c_int, [_vp, _dp, _dp, _dp, _dp]),
     "lbt1_grid3d_reduce": (ctypes.c_int, [_vp, ctypes.c_uint32, _dp]),
+    "lbt1_grid3d_set_kernel": (ctypes.c_int, [_vp, _i32]),
+    "lbt1_grid3d_get_kernel": (ctypes.c_int, [_vp, ctypes.POINTER(_i32)]),
     "lbt1_grid3d_sync": (ctypes.c_int, [_vp]),
     "lbt1_grid3d_destroy": (ctypes.c_int, [_vp]),
 }

@@ -72,6 +72,17 @@ static const void *step3_kernel(int prec, int q, bool haswall, int wall) {
   return nullptr;
 }
 
+constexpr int kZChunk = 16;  // planes a tile block marches through
+
+static const void *tile3_kernel(int prec, int q) {
+#define T3(P, Q) \
+  if (prec == P && q == Q) return (const void *)&k_step3_tile<P, Q, kZChunk>;
+  T3(P_F64, 19) T3(P_F64, 27) T3(P_F32, 19) T3(P_F32, 27) T3(P_F16S, 19) T3(P_F16S, 27) T3(P_BF16S, 19)
+  T3(P_BF16S, 27)
+#undef T3
+  return nullptr;
+}
+
 static const void *reduce3_kernel(int prec) {
   switch (prec) {
     case P_F64: return (const void *)&k_reduce3_partial<P_F64>;
@@ -103,8 +114,22 @@ struct lbt1_grid3d {
   double *partials = nullptr, *red_out = nullptr, *red_host = nullptr;
   int parity = 0;
   bool geometry = false, haswall = false;
+  int want = LBT1_KERNEL_AUTO;  // kernel family asked for
+  bool tile = false;            // the z-marching LDS tile kernel is bound
   const void *kern = nullptr;
 };
+
+// AUTO and STRIP take the tile kernel on grids periodic in all axes without wall
+// or fixed nodes; GATHER (and AUTO elsewhere) the one-thread-per-node kernel.
+static lbt1_status bind3(lbt1_grid3d *g) {
+  const bool can_tile = !g->haswall;
+  if (g->want == LBT1_KERNEL_STRIP && !can_tile)
+    return fail(LBT1_EINVAL, "the 3-D tile kernel needs a grid periodic in x, y, z without SOLID or FIXED nodes");
+  g->tile = g->want != LBT1_KERNEL_GATHER && can_tile;
+  g->kern = g->tile ? tile3_kernel(g->prec, g->q) : step3_kernel(g->prec, g->q, g->haswall, g->wall);
+  if (!g->kern) return fail(LBT1_EINVAL, "no built 3-D kernel");
+  return LBT1_OK;
+}
 
 static Step3Args step3_args(const lbt1_grid3d *g, int p) {
   Step3Args a{};
@@ -273,10 +298,34 @@ lbt1_status lbt1_grid3d_set_geometry(lbt1_grid3d *g, const uint8_t *flags, const
   if ((e = hipMemcpy(g->flags, fstage.data(), fstage.size(), hipMemcpyHostToDevice)) != hipSuccess)
     return hip_fail(e, "hipMemcpy H2D");
   g->haswall = any_nonfluid || g->periodic != 7u;
-  g->kern = step3_kernel(g->prec, g->q, g->haswall, g->wall);
-  if (!g->kern) return fail(LBT1_EINVAL, "no built 3-D kernel");
+  lbt1_status st = bind3(g);
+  if (st) return st;
   g->parity = 0;
   g->geometry = true;
+  return LBT1_OK;
+}
+
+lbt1_status lbt1_grid3d_set_kernel(lbt1_grid3d *g, int32_t kernel) {
+  clear_error();
+  if (!g) return fail(LBT1_EINVAL, "null grid");
+  if (kernel != LBT1_KERNEL_AUTO && kernel != LBT1_KERNEL_GATHER && kernel != LBT1_KERNEL_STRIP)
+    return fail(LBT1_EINVAL, "unknown kernel family %d", kernel);
+  const int old = g->want;
+  g->want = kernel;
+  if (!g->geometry) return LBT1_OK;
+  lbt1_status st = bind3(g);
+  if (st) {
+    g->want = old;
+    bind3(g);
+  }
+  return st;
+}
+
+lbt1_status lbt1_grid3d_get_kernel(lbt1_grid3d *g, int32_t *kernel) {
+  clear_error();
+  if (!g || !kernel) return fail(LBT1_EINVAL, "null argument");
+  if (!g->geometry) return fail(LBT1_ESTATE, "no geometry set");
+  *kernel = g->tile ? LBT1_KERNEL_STRIP : LBT1_KERNEL_GATHER;
   return LBT1_OK;
 }
 
@@ -287,7 +336,10 @@ lbt1_status lbt1_grid3d_step(lbt1_grid3d *g, int64_t n) {
   if (!g->geometry) return fail(LBT1_ESTATE, "step before set_geometry");
   hipError_t e;
   if ((e = hipSetDevice(g->device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
-  const dim3 block(64, 4, 1), grid((g->nx + 63) / 64, (g->ny + 3) / 4, g->nz);
+  const dim3 block = g->tile ? dim3(256, 1, 1) : dim3(64, 4, 1);
+  const dim3 grid = g->tile ? dim3((g->nx + kTile3X - 1) / kTile3X, (g->ny + kTile3Y - 1) / kTile3Y,
+                                   (g->nz + kZChunk - 1) / kZChunk)
+                            : dim3((g->nx + 63) / 64, (g->ny + 3) / 4, g->nz);
   for (int64_t s = 0; s < n; ++s) {
     Step3Args a = step3_args(g, g->parity);
     void *args[] = {&a};

@@ -143,6 +143,86 @@ __global__ void __launch_bounds__(256) k_step3_gather(Step3Args a) {
   static_cast<S *>(a.dst[3])[i] = T::enc(zn);
 }
 
+// Periodic grids without wall or fixed nodes: a block of 64 x 4 nodes marches
+// along z through ZC planes.  Three planes of its tile plus a one-node halo
+// live in LDS as the per-source values every emission needs (J, s = 4.5 / rho,
+// b = d - 1.5 |J|^2 / rho), computed once per node and plane; each target then
+// forms its Q arrivals from LDS.  The per-direction arithmetic is that of the
+// gather kernel, so the two give the same bits.
+constexpr int kTile3X = 64, kTile3Y = 4;
+constexpr int kHalo3X = kTile3X + 2, kHalo3Y = kTile3Y + 2, kHalo3N = kHalo3X * kHalo3Y;
+
+template <int P, int Q, int ZC>
+__global__ void __launch_bounds__(256) k_step3_tile(Step3Args a) {
+  using T = Traits<P>;
+  using C = typename T::C;
+  using S = typename T::S;
+  __shared__ C sJx[3][kHalo3N], sJy[3][kHalo3N], sJz[3][kHalo3N], sS[3][kHalo3N], sB[3][kHalo3N];
+  const int tid = threadIdx.x;
+  const int tx = tid & 63, ty = tid >> 6;
+  const int x0 = blockIdx.x * kTile3X, y0 = blockIdx.y * kTile3Y, z0 = blockIdx.z * ZC;
+  const C Fx = C(a.fx), Fy = C(a.fy), Fz = C(a.fz);
+  // load plane z (wrapped) of the halo tile into LDS slot `slot`
+  auto load_plane = [&](int z, int slot) __attribute__((always_inline)) {
+    const int zz = wrap_axis(z, a.nz, true);
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const int h = tid + r * 256;
+      if (h < kHalo3N) {
+        const int hx = h % kHalo3X, hy = h / kHalo3X;
+        const int gx = wrap_axis(x0 - 1 + hx, a.nx, true), gy = wrap_axis(y0 - 1 + hy, a.ny, true);
+        C d, jx, jy, jz;
+        load3<P>(a, (long)zz * a.zs + (long)gy * a.rs + gx, d, jx, jy, jz);
+        const C inv = recip<C>(C(1) + d);
+        const C Jx = jx + Fx, Jy = jy + Fy, Jz = jz + Fz;
+        const C t = (Jx * Jx + Jy * Jy + Jz * Jz) * inv;
+        sJx[slot][h] = Jx;
+        sJy[slot][h] = Jy;
+        sJz[slot][h] = Jz;
+        sS[slot][h] = C(4.5) * inv;
+        sB[slot][h] = fmaC<C>(C(-1.5), t, d);
+      }
+    }
+  };
+  load_plane(z0 - 1, 0);
+  load_plane(z0, 1);
+  const int x = x0 + tx, y = y0 + ty;
+  const bool out = x < a.nx && y < a.ny;
+  for (int k = 0; k < ZC; ++k) {
+    const int z = z0 + k;
+    if (z >= a.nz) break;  // uniform across the block
+    load_plane(z + 1, (k + 2) % 3);
+    __syncthreads();
+    if (out) {
+      C dn = C(0), xn = C(0), yn = C(0), zn = C(0);
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const int slot = (k + 1 - k3z[q] + 3) % 3;  // plane z - e_z
+        const int h = (ty + 1 - k3y[q]) * kHalo3X + (tx + 1 - k3x[q]);
+        const C Jx = sJx[slot][h], Jy = sJy[slot][h], Jz = sJz[slot][h];
+        const C eJ = add_comp<C>(add_comp<C>(add_comp<C>(C(0), k3x[q], Jx), k3y[q], Jy), k3z[q], Jz);
+        const C f = C(w3<Q>(q)) * fmaC<C>(sS[slot][h], eJ * eJ, fmaC<C>(C(3), eJ, sB[slot][h]));
+        dn += f;
+        xn = add_comp<C>(xn, k3x[q], f);
+        yn = add_comp<C>(yn, k3y[q], f);
+        zn = add_comp<C>(zn, k3z[q], f);
+      }
+      if (T::kScaled) {
+        dn *= C(a.is_d);
+        xn *= C(a.is_j);
+        yn *= C(a.is_j);
+        zn *= C(a.is_j);
+      }
+      const long i = (long)z * a.zs + (long)y * a.rs + x;
+      static_cast<S *>(a.dst[0])[i] = T::enc(dn);
+      static_cast<S *>(a.dst[1])[i] = T::enc(xn);
+      static_cast<S *>(a.dst[2])[i] = T::enc(yn);
+      static_cast<S *>(a.dst[3])[i] = T::enc(zn);
+    }
+    __syncthreads();  // the slot of plane z - 1 is refilled next
+  }
+}
+
 struct Reduce3Args {
   const void *cur[4];
   void *snap[4];

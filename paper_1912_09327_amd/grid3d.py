@@ -42,6 +42,16 @@ class Grid3D:
                                                *[None if a is None else _dptr(a) for a in arrs]))
         return self
 
+    def set_kernel(self, kernel="auto"):
+        k = {"auto": C.KERNEL_AUTO, "gather": C.KERNEL_GATHER, "tile": C.KERNEL_STRIP}[kernel]
+        C.check(C.lib.lbt1_grid3d_set_kernel(self.handle, k))
+        return self
+
+    def kernel(self):
+        k = ctypes.c_int32()
+        C.check(C.lib.lbt1_grid3d_get_kernel(self.handle, ctypes.byref(k)))
+        return "tile" if k.value == C.KERNEL_STRIP else "gather"
+
     def step(self, n=1):
         C.check(C.lib.lbt1_grid3d_step(self.handle, int(n)))
         return self

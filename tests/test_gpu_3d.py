@@ -124,3 +124,42 @@ def test_3d_errors():
         g.step(2)
     finally:
         g.close()
+
+
+@pytest.mark.parametrize("q", [19, 27])
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16s"])
+@pytest.mark.parametrize("shape", [(9, 21, 70), (16, 4, 64), (20, 7, 130), (1, 3, 5)])
+def test_3d_tile_bitwise_equals_gather(shape, prec, q):
+    from paper_1912_09327_amd.grid3d import Grid3D
+    flags, rho, js, per = _case("periodic", shape, 7)
+    nz, ny, nx = shape
+    F = (1e-5, 2e-6, -3e-6)
+    out = {}
+    for kern in ("gather", "tile"):
+        g = Grid3D(nx, ny, nz, q=q, prec=prec, periodic=per, force=F)
+        try:
+            g.set_kernel(kern)
+            g.set_geometry(flags, rho, *js)
+            assert g.kernel() == kern
+            g.step(11)
+            out[kern] = g.read_moments()
+        finally:
+            g.close()
+    for a, b in zip(out["gather"], out["tile"]):
+        assert np.array_equal(a, b)
+
+
+def test_3d_tile_refused_with_walls():
+    from paper_1912_09327_amd import _capi as C
+    from paper_1912_09327_amd.grid3d import Grid3D
+    flags, rho, js, per = _case("plates", (8, 8, 64), 8)
+    g = Grid3D(64, 8, 8, q=19, periodic=per)
+    try:
+        g.set_geometry(flags, rho, *js)
+        assert g.kernel() == "gather"
+        with pytest.raises(C.Lbt1Error) as e:
+            g.set_kernel("tile")
+        assert e.value.status == C.EINVAL
+        g.step(2)
+    finally:
+        g.close()
