@@ -70,6 +70,7 @@ def parse():
     p.add_argument("--cavities", type=int, default=512)
     p.add_argument("--max-steps", type=int, default=200000)
     p.add_argument("--requests", type=int, default=200)
+    p.add_argument("--budget-mib", type=int, default=1024, help="serve: HBM budget of the server")
     p.add_argument("--load", type=float, default=0.7)
     return p.parse_args()
 

@@ -47,7 +47,7 @@ class Result:
     admitted: float
     finished: float
     steps: int
-    state: str              # "budget" | "converged" | "nonfinite"
+    state: str              # "budget" | "converged" | "nonfinite" | "refused"
     residual: float
     lups: float             # fluid node updates done
     moments: tuple = field(default=None, repr=False)
@@ -217,7 +217,14 @@ class Server:
                 req = queue[0]
                 nbytes = self.b.grid_bytes(req)
                 if nbytes > self.budget:
-                    raise ValueError(f"request {req.id} needs {nbytes} B, more than the whole budget")
+                    # can never fit: refused at once, the queue moves on
+                    queue.popleft()
+                    geo.pop(req.id).cancel()
+                    now = self.clock() - t0
+                    done.append(Result(req.id, req.arrival, now, now, 0, "refused", float("nan"), 0.0))
+                    if self.progress:
+                        self.progress(len(done), now)
+                    continue
                 if used + nbytes > self.budget:
                     break
                 handle = self.b.create(req, geo.pop(req.id).result())
@@ -252,8 +259,10 @@ class Server:
 class PlainFifo:
     """One request at a time, in arrival order, one launch per step."""
 
-    def __init__(self, backend, burst=100, keep_results=False, clock=None, sleep=None, progress=None):
+    def __init__(self, backend, burst=100, keep_results=False, clock=None, sleep=None, progress=None,
+                 budget=None):
         self.b = backend
+        self.budget = budget           # requests larger than this are refused (None: no limit)
         self.burst = int(burst)
         self.keep = keep_results
         self.clock = clock or time.perf_counter
@@ -274,6 +283,11 @@ class PlainFifo:
             g = nxt.result()
             # the next request's geometry is built while this one runs
             nxt = pool.submit(geometry, order[k + 1]) if k + 1 < len(order) else None
+            if self.budget is not None and self.b.grid_bytes(req) > self.budget:
+                done.append(Result(req.id, req.arrival, adm, adm, 0, "refused", float("nan"), 0.0))
+                if self.progress:
+                    self.progress(len(done), adm)
+                continue
             handle = self.b.create(req, g)
             state, steps, res = self.b.run_alone(handle, req.steps, req.tol, self.burst)
             now = self.clock() - t0
@@ -288,11 +302,14 @@ class PlainFifo:
 
 
 def summarize(results, wall_seconds=None):
-    """p50 / p99 latency, aggregate MLUPS and counts of a finished run."""
-    lat = np.array([r.latency for r in results])
-    lups = sum(r.lups for r in results)
+    """p50 / p99 latency (over the requests served; refused ones are counted apart),
+    aggregate MLUPS and counts of a finished run."""
+    served = [r for r in results if r.state != "refused"]
+    lat = np.array([r.latency for r in served]) if served else np.zeros(1)
+    lups = sum(r.lups for r in served)
     if wall_seconds is None:
         wall_seconds = max(r.finished for r in results) - min(r.arrival for r in results)
-    return dict(n=len(results), p50_s=float(np.percentile(lat, 50)), p99_s=float(np.percentile(lat, 99)),
-                mean_s=float(lat.mean()), mlups=lups / wall_seconds / 1e6, wall_s=wall_seconds,
+    return dict(n=len(results), served=len(served), p50_s=float(np.percentile(lat, 50)),
+                p99_s=float(np.percentile(lat, 99)), mean_s=float(lat.mean()),
+                mlups=lups / max(wall_seconds, 1e-12) / 1e6, wall_s=wall_seconds,
                 states=dict(collections.Counter(r.state for r in results)))

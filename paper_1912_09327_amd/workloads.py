@@ -128,7 +128,7 @@ def bench_cavities(args, torch, log):
 
 def bench_serve(args, torch, log):
     from .serve import GpuBackend, PlainFifo, Server, requests_from_stream, summarize
-    budget = 1 << 30
+    budget = int(getattr(args, "budget_mib", 1024)) << 20
     slots = 64
 
     def progress(tag):
@@ -157,7 +157,7 @@ def bench_serve(args, torch, log):
     log(f"[serve] server: p50 {s_srv['p50_s']:.3f} s p99 {s_srv['p99_s']:.3f} s {s_srv['mlups']:.0f} MLUPS")
     be = GpuBackend(budget, 1, prec="f16s")
     t0 = time.perf_counter()
-    plain = PlainFifo(be, progress=progress("plain")).serve(reqs)
+    plain = PlainFifo(be, progress=progress("plain"), budget=budget).serve(reqs)
     wall_p = time.perf_counter() - t0
     be.close()
     s_pl = summarize(plain, wall_p)
@@ -177,8 +177,9 @@ def bench_serve(args, torch, log):
         "data": "synthetic",
         "config": {"workload": f"{len(reqs)} Poisson requests at {rate:.3f}/s (load {args.load} of the "
                                f"measured capacity {cap:.3f}/s), half cavities half porous channels, "
-                               "side 32..2048, budgets 1e3..1e5 steps, FP16 storage, 1 GiB HBM budget, 64 slots",
-                   "requests": len(reqs), "rate_per_s": rate, "load": args.load},
+                               f"side 32..2048, budgets 1e3..1e5 steps, FP16 storage, {budget >> 20} MiB HBM "
+                               "budget, 64 slots",
+                   "requests": len(reqs), "rate_per_s": rate, "load": args.load, "budget_mib": budget >> 20},
         "server": s_srv,
         "plain": s_pl,
     }

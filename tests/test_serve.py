@@ -186,9 +186,19 @@ def test_nonfinite_grid_is_reported_and_isolated():
 
 
 def test_request_larger_than_the_budget_is_refused():
+    """A request that can never fit is refused at once; the others are served."""
+    reqs = _reqs(4)
+    reqs[1].L = 200                                   # 200^2 * 13 B > the budget below
+    budget = 30 * 30 * OracleBackend.BYTES_PER_NODE
     be = OracleBackend(FakeClock(), slots=2)
-    with pytest.raises(ValueError):
-        Server(be, 100, 2, clock=be.clock, sleep=be.clock.sleep).serve(_reqs(1))
+    res = {r.id: r for r in Server(be, budget, 2, clock=be.clock, sleep=be.clock.sleep).serve(reqs)}
+    assert res[1].state == "refused" and res[1].steps == 0
+    assert all(res[i].state == "budget" for i in (0, 2, 3))
+    be2 = OracleBackend(FakeClock(), slots=1)
+    plain = {r.id: r for r in PlainFifo(be2, clock=be2.clock, sleep=be2.clock.sleep, budget=budget).serve(reqs)}
+    assert plain[1].state == "refused" and all(plain[i].state == "budget" for i in (0, 2, 3))
+    s = summarize(list(res.values()))
+    assert s["served"] == 3 and s["states"]["refused"] == 1
 
 
 def test_request_stream_shapes():
