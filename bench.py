@@ -161,9 +161,24 @@ def cpu_baseline(state, budget_s):
     t0 = time.perf_counter()
     oracle.run(*sub, n, None, 3)
     dt = time.perf_counter() - t0
-    return dict(value=round(m * m * n / dt / 1e6, 2), unit="MLUPS", cores=threads, kind="oracle",
-                sample=f"{m}x{m} periodic window of the same seed-0 random field, {n} steps, "
-                       f"FP64, {threads} OpenMP threads, {dt:.1f} s")
+    out = dict(value=round(m * m * n / dt / 1e6, 2), unit="MLUPS", cores=threads, kind="oracle",
+               sample=f"{m}x{m} periodic window of the same seed-0 random field, {n} steps, "
+                      f"FP64, {threads} OpenMP threads, {dt:.1f} s")
+    # the same oracle on one thread, a 512 x 512 window for about a third of the budget
+    oracle.set_threads(1)
+    s = 512
+    sub1 = [np.ascontiguousarray(a[:s, :s]) for a in state]
+    t0 = time.perf_counter()
+    oracle.run(*sub1, 5, None, 3)
+    one = (time.perf_counter() - t0) / 5
+    n1 = max(1, int(budget_s / 3 / max(one, 1e-4)))
+    t0 = time.perf_counter()
+    oracle.run(*sub1, n1, None, 3)
+    dt1 = time.perf_counter() - t0
+    oracle.set_threads(threads)
+    out["single_thread"] = dict(value=round(s * s * n1 / dt1 / 1e6, 2), unit="MLUPS",
+                                sample=f"{s}x{s} window, {n1} steps, FP64, 1 thread, {dt1:.1f} s")
+    return out
 
 
 def field_error(a, ref):
