@@ -32,6 +32,7 @@ __global__ void __launch_bounds__(64) k_reduce_final(const double *partials, int
   {P, false, 0, KIND_STRIP, V, R, (const void *)&k_step_fused<P, V, R, K>, \
    "k_step_fused<" #P "," #V "," #R "," #K ">", K, 0}
 #define FUSED_ROWS(P, V, K) FUSED(P, V, 6, K), FUSED(P, V, 14, K)
+#define FUSED_TALL(P, V, K) FUSED(P, V, 22, K), FUSED(P, V, 30, K)
 #define STRIP_WALLS(P, V, R) STRIP(P, false, 0, V, R), STRIP(P, true, 0, V, R), STRIP(P, true, 1, V, R)
 #define STRIP_ROWS(P, V) STRIP_WALLS(P, V, 6), STRIP_WALLS(P, V, 14)
 // 8 columns per lane only without walls: the wall-aware variants at that width
@@ -58,7 +59,12 @@ static const StepKernel kTable[] = {
     STRIP_ROWS(P_F32, 4),  STRIP_ROWS(P_F16S, 1), STRIP_ROWS(P_F16S, 2), STRIP_ROWS(P_F16S, 4),
     STRIP_ROWS_NOWALL(P_F16S, 8), STRIP_ROWS(P_BF16S, 1), STRIP_ROWS(P_BF16S, 2), STRIP_ROWS(P_BF16S, 4),
     STRIP_ROWS_NOWALL(P_BF16S, 8),
-    // two steps per launch; four would need more registers than a wavefront has
+    // two steps per launch, and three at 4 columns per lane (FP32, FP16S; FP64 would
+    // need scratch memory); four would need more registers than a wavefront has
+    FUSED_ROWS(P_F32, 4, 3),   FUSED_ROWS(P_F16S, 4, 3),
+    // taller strips: fewer redundant halo rows per stored row (FP32 at 30 rows
+    // would need scratch memory)
+    FUSED(P_F32, 4, 22, 2),    FUSED_TALL(P_F16S, 2, 2),  FUSED_TALL(P_BF16S, 2, 2),
     FUSED_ROWS(P_F64, 2, 2),   FUSED_ROWS(P_F32, 2, 2),   FUSED_ROWS(P_F32, 4, 2),
     FUSED_ROWS(P_F16S, 2, 2),  FUSED_ROWS(P_F16S, 4, 2),  FUSED_ROWS(P_BF16S, 2, 2),
     FUSED_ROWS(P_BF16S, 4, 2),

@@ -287,16 +287,20 @@ lbt1_kernel_config heuristic_config(int prec, bool haswall, int wall, int nx, in
   c.vec = 1;
   c.fuse = 1;
   if (!haswall) {
-    // two steps per pass (measured fastest on large periodic grids): 4 columns per
-    // lane in FP32, 2 in FP64 (registers) and in 16-bit storage (arithmetic-bound)
+    // several steps per pass (measured fastest on large periodic grids): FP32 three
+    // steps at 4 columns per lane; FP64 two at 2 (registers); 16-bit storage two at
+    // 2 columns and tall strips (arithmetic-bound, so fewer redundant halo rows)
+    const bool half = prec == LBT1_F16S || prec == LBT1_BF16S;
     const int v = prec == LBT1_F32 ? 4 : 2;
+    const int k = prec == LBT1_F32 ? 3 : 2;
     if (nx % v == 0 && 62 * v <= std::max(62, nx)) {
-      const long tall = (long)((nx / v + 61) / 62) * ((ny + 13) / 14);
-      const int r = (prec == LBT1_F16S || prec == LBT1_BF16S) && tall >= 8L * cus ? 14 : 6;
-      if (find_kernel(prec, false, 0, KIND_STRIP, v, r, 2, false)) {
+      const long tall = (long)((nx / v + 61) / 62) * ((ny + 29) / 30);
+      const int r = half ? (tall >= 8L * cus ? 30 : 6) : (prec == LBT1_F32 ? 14 : 6);
+      if (find_kernel(prec, false, 0, KIND_STRIP, v, r, k, false)) {
         c.vec = v;
         c.rows = r;
-        c.fuse = 2;
+        c.fuse = k;
+        c.waves = prec == LBT1_F32 ? 8 : 0;
         return c;
       }
     }
@@ -324,8 +328,8 @@ lbt1_status bind_config(lbt1_grid *g, const lbt1_kernel_config &want, int cus) {
     g->cfg.kernel = LBT1_KERNEL_GATHER;
     g->cfg.fuse = 1;
     const int tiles = ((g->nx + 63) / 64) * ((g->ny + 3) / 4);
-    g->block = dim3(256, 1, 1);
-    g->grid = dim3((tiles + 7) / 8 * 8, 1, 1);
+    g->block = g->block1 = dim3(256, 1, 1);
+    g->grid = g->grid1 = dim3((tiles + 7) / 8 * 8, 1, 1);
     g->graph_valid = false;
     return LBT1_OK;
   }
@@ -353,6 +357,9 @@ lbt1_status bind_config(lbt1_grid *g, const lbt1_kernel_config &want, int cus) {
       return fail(LBT1_EINVAL, "multiphase strips need a grid periodic in x and y without SOLID nodes (use gather)");
     k = find_kernel(g->prec, g->haswall, g->wall, KIND_STRIP, c.vec, c.rows, c.fuse, g->mp);
     k1 = find_kernel(g->prec, g->haswall, g->wall, KIND_STRIP, c.vec, c.rows, 1, g->mp);
+    // a fused shape with no single-step strip of its height finishes odd step
+    // counts with the gather kernel (same arithmetic, own launch shape)
+    if (k && !k1 && c.fuse > 1) k1 = find_kernel(g->prec, g->haswall, g->wall, KIND_GATHER, 0, 0, 1, g->mp);
   } else {
     return fail(LBT1_EINVAL, "unknown kernel family %d", c.kernel);
   }
@@ -384,6 +391,12 @@ lbt1_status bind_config(lbt1_grid *g, const lbt1_kernel_config &want, int cus) {
     m.per_xcd = (m.units + 7) / 8;
     g->block = dim3(256, 1, 1);
     g->grid = dim3(blocks, 1, 1);
+  }
+  g->block1 = g->block;
+  g->grid1 = g->grid;
+  if (k1->kind == KIND_GATHER && k->kind != KIND_GATHER) {
+    g->block1 = dim3(64, 4, 1);
+    g->grid1 = dim3((g->nx + 63) / 64, (g->ny + 3) / 4, 1);
   }
   g->graph_valid = false;
   return LBT1_OK;
@@ -457,24 +470,27 @@ hipError_t launch_step(lbt1_grid *g, const StepKernel *k, int src_parity, hipStr
   StepArgs a = step_args(g, src_parity);
   if (k->kind == KIND_GATHER) {
     void *args[] = {&a};
-    return hipLaunchKernel(k->fn, g->grid, g->block, args, 0, s);
+    const bool companion = k == g->kern1 && k != g->kern;
+    return hipLaunchKernel(k->fn, companion ? g->grid1 : g->grid, companion ? g->block1 : g->block, args, 0, s);
   }
   StripMap m = g->map;
   void *args[] = {&a, &m};
   return hipLaunchKernel(k->fn, g->grid, g->block, args, 0, s);
 }
 
-// A graph of launches covering kBurst steps starting from parity p.  A launch
-// advances g->kern->steps steps (1 or 2) and flips the parity once; kBurst /
-// steps is even, so the parity after a replay is p again.
+// A graph of kBurst / K launches (K = g->kern->steps) starting from parity p:
+// it advances burst_steps(g) steps and flips the parity once per launch.
 static const int kBurst = 64;
+
+static int burst_launches(const lbt1_grid *g) { return kBurst / g->kern->steps; }
+static int burst_steps(const lbt1_grid *g) { return burst_launches(g) * g->kern->steps; }
 
 static lbt1_status build_burst(lbt1_grid *g, int p) {
   hipGraph_t graph = nullptr;
   hipError_t e = hipGraphCreate(&graph, 0);
   if (e != hipSuccess) return hip_fail(e, "hipGraphCreate");
   hipGraphNode_t prev = nullptr;
-  const int launches = kBurst / g->kern->steps;
+  const int launches = burst_launches(g);
   std::vector<StepArgs> argv(launches);
   std::vector<BgkArgs> bargv(g->pop ? launches : 0);
   StripMap m = g->map;
@@ -528,20 +544,22 @@ static void drop_bursts(lbt1_grid *g) {
 
 lbt1_status enqueue_steps(lbt1_grid *g, int64_t n, hipStream_t s, bool use_graph) {
   hipError_t e;
-  if (use_graph && n >= kBurst) {
+  const int bs = burst_steps(g);
+  if (use_graph && n >= bs) {
     if (!g->graph_valid) {
       drop_bursts(g);
       g->graph_valid = true;
     }
-    while (n >= kBurst) {
+    while (n >= bs) {
       const int p = g->parity;
       if (!g->burst[p]) {
         lbt1_status st = build_burst(g, p);
         if (st) return st;
       }
       if ((e = hipGraphLaunch(g->burst[p], s)) != hipSuccess) return hip_fail(e, "hipGraphLaunch");
-      n -= kBurst;
-      g->steps += kBurst;
+      n -= bs;
+      g->steps += bs;
+      g->parity ^= burst_launches(g) & 1;
     }
   }
   const int K = g->kern->steps;
@@ -1124,9 +1142,9 @@ lbt1_status lbt1_autotune(lbt1_grid *g, int32_t steps, int32_t reps, lbt1_kernel
     cands.push_back(c);
   }
   const int vecs[] = {1, 2, 4, 8};
-  const int rows[] = {6, 14};
+  const int rows[] = {6, 14, 22, 30};
   const int waves[] = {0, 8, 16};
-  const int fuses[] = {1, 2};
+  const int fuses[] = {1, 2, 3};
   for (int v : vecs)
     for (int r : rows)
       for (int w : waves)
@@ -1145,7 +1163,7 @@ lbt1_status lbt1_autotune(lbt1_grid *g, int32_t steps, int32_t reps, lbt1_kernel
           cands.push_back(c);
         }
   // a whole number of fused launches for every candidate
-  steps = (steps + 1) / 2 * 2;
+  steps = (steps + 5) / 6 * 6;
   double best_ms = 1e300;
   lbt1_kernel_config bc = g->cfg;
   lbt1_status st = LBT1_OK;

@@ -81,6 +81,7 @@ struct lbt1_grid {
   const lbt1::StepKernel *kern1 = nullptr;  // single-step kernel of the same launch shape
   lbt1::StripMap map{};
   dim3 grid{1, 1, 1}, block{1, 1, 1};
+  dim3 grid1{1, 1, 1}, block1{1, 1, 1};  // launch shape of kern1
   hipGraphExec_t burst[2] = {nullptr, nullptr};
   bool graph_valid = false;
   // batch residency

@@ -40,8 +40,10 @@ def test_fused_bitwise_equals_single_steps(prec, shape):
 
 
 @pytest.mark.parametrize("prec", ["f32", "f16s"])
-def test_fused_graph_bursts_and_splitting(prec):
-    """Bursts of 64 steps (32 fused launches), odd remainders and split calls."""
+@pytest.mark.parametrize("vec,fuse", [(2, 2), (4, 3)])
+def test_fused_graph_bursts_and_splitting(prec, vec, fuse):
+    """Bursts (32 launches of two steps; 21 launches of three, which flip the parity),
+    odd remainders and split calls."""
     from paper_1912_09327_amd.grid import Grid
     nx, ny = 372, 90
     rho, jx, jy = _state(nx, ny, 5)
@@ -49,7 +51,7 @@ def test_fused_graph_bursts_and_splitting(prec):
     g = Grid(nx, ny, prec=prec, periodic=3)
     try:
         g.set_geometry(None, rho, jx, jy)
-        g.set_kernel("strip", vec=2, rows=14, waves=0, fuse=2)
+        g.set_kernel("strip", vec=vec, rows=14, waves=0, fuse=fuse)
         for n in (1, 64, 3, 128, 21):
             g.step(n)
         got = g.read_moments()
@@ -57,6 +59,21 @@ def test_fused_graph_bursts_and_splitting(prec):
         g.close()
     for a, b in zip(ref, got):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("prec", ["f32", "f16s"])
+@pytest.mark.parametrize("shape", [(512, 77), (248, 64), (8, 5)])
+def test_three_fused_steps_bitwise(prec, shape):
+    nx, ny = shape
+    rho, jx, jy = _state(nx, ny, 33)
+    F = (1e-5, -2e-6)
+    base = gpu_run(None, rho, jx, jy, 26, prec, "paper", 3, F, kernel=dict(kernel="gather"))
+    for rows in (6, 14):
+        for waves in (0, 8):
+            cfg = dict(kernel="strip", vec=4, rows=rows, waves=waves, fuse=3)
+            got = gpu_run(None, rho, jx, jy, 26, prec, "paper", 3, F, kernel=cfg)
+            for a, b in zip(base, got):
+                assert np.array_equal(a, b), (rows, waves)
 
 
 def test_fused_f64_matches_oracle():
@@ -97,3 +114,17 @@ def test_fused_refused_where_it_does_not_apply():
         g.step(3)
     finally:
         g.close()
+
+
+@pytest.mark.parametrize("prec,vec,rows", [("f32", 4, 22), ("f16s", 2, 22), ("f16s", 2, 30),
+                                           ("bf16s", 2, 30)])
+@pytest.mark.parametrize("shape", [(512, 77), (248, 33)])
+def test_tall_fused_strips_bitwise(prec, vec, rows, shape):
+    nx, ny = shape
+    rho, jx, jy = _state(nx, ny, 41)
+    base = gpu_run(None, rho, jx, jy, 25, prec, "paper", 3, (1e-5, 0.0), kernel=dict(kernel="gather"))
+    for waves in (0, 8):
+        got = gpu_run(None, rho, jx, jy, 25, prec, "paper", 3, (1e-5, 0.0),
+                      kernel=dict(kernel="strip", vec=vec, rows=rows, waves=waves, fuse=2))
+        for a, b in zip(base, got):
+            assert np.array_equal(a, b), waves
