@@ -89,22 +89,26 @@ def make_grid(n, storage, state, tune=True, kernel=None, planar=False):
             f = parts[4] if len(parts) > 4 else 1
             g.set_kernel("strip", int(v), int(r), int(w), int(f))
     elif tune:
-        g.autotune(steps=10, reps=2)
+        g.autotune(steps=30, reps=3)
     return g
 
 
-def timed_run(g, steps, warmup, torch):
-    """Warm up, then time exactly `steps` steps: reductions every 100 steps, HIP events
-    around every block of step launches on the grid's stream."""
+def timed_run(g, steps, warmup, torch, per_launch=1):
+    """Warm up, then time exactly `steps` steps: a reduction after every block of about
+    100 steps, HIP events around every block of step launches on the grid's stream.
+    A block is a whole number of launches of `per_launch` steps (99 steps for three),
+    so only the last block can end in a shorter launch; the per-step kernel time
+    comes from the whole-launch blocks."""
     s = g.stream
     g.step(warmup)
     g.reduce()
     torch.cuda.synchronize()
     ev = []
+    block = max(per_launch, 100 // per_launch * per_launch)
     t0 = time.perf_counter()
     done = 0
     while done < steps:
-        k = min(100, steps - done)
+        k = min(block, steps - done)
         a = torch.cuda.Event(enable_timing=True)
         b = torch.cuda.Event(enable_timing=True)
         a.record(s)
@@ -112,12 +116,12 @@ def timed_run(g, steps, warmup, torch):
         b.record(s)
         ev.append((a, b, k))
         done += k
-        if done % 100 == 0 or done == steps:
-            g.reduce()                   # FP64 mass / residual / non-finite, synchronises
+        g.reduce()                       # FP64 mass / residual / non-finite, synchronises
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    kern_ms = sum(a.elapsed_time(b) for a, b, _ in ev)
-    return wall, kern_ms / steps
+    whole = [(a, b, k) for a, b, k in ev if k % per_launch == 0] or ev
+    kern_ms = sum(a.elapsed_time(b) for a, b, _ in whole)
+    return wall, kern_ms / sum(k for _, _, k in whole)
 
 
 def copy_ceiling(nbytes=2 << 30):
@@ -240,9 +244,9 @@ def run_periodic(args, torch):
         g = make_grid(n, storage, state, tune=not args.no_tune, kernel=args.kernel, planar=args.planar)
         cfg, kname = g.kernel()
         log(f"[bench] {storage}: kernel {kname} {cfg}")
-        wall, kms = timed_run(g, args.steps, args.warmup, torch)
-        c = VALUE_BYTES[storage]
         K = max(1, cfg.get("fuse", 1)) if cfg.get("kernel") == 2 else 1   # steps per launch
+        wall, kms = timed_run(g, args.steps, args.warmup, torch, K)
+        c = VALUE_BYTES[storage]
         launch_ms = kms * K
         achieved = 2 * 3 * c * lups / (launch_ms * 1e-3) / 1e9
         results[storage] = dict(mlups=lups * args.steps / wall / 1e6, ms_per_step=wall * 1e3 / args.steps,
@@ -271,7 +275,8 @@ def run_periodic(args, torch):
         "config": {"workload": f"periodic {n}x{n} random field (rho = 1 + 1e-3 N(0,1), "
                                f"u = 0.01 N(0,1), seed 0), {args.storage} moment storage",
                    "nx": n, "ny": n, "storage": args.storage, "fluid_nodes": int(lups),
-                   "reduction_every": 100, "kernel": head["kernel"], "kernel_config": head["config"]},
+                   "reduction_every": max(head["steps_per_launch"], 100 // head["steps_per_launch"] * head["steps_per_launch"]),
+                   "kernel": head["kernel"], "kernel_config": head["config"]},
         "roofline": {"bound": "hbm", "achieved": round(head["achieved"], 1), "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": round(head["achieved"] / HBM_PEAK_GBPS, 4), "traffic": None,
                      "bytes_per_launch": 2 * 3 * c * int(lups), "steps_per_launch": head["steps_per_launch"],
@@ -337,8 +342,8 @@ def run_compare(args, torch):
             g.set_kernel(*kern)
         cfg, kname = g.kernel()
         log(f"[compare] {name}: {kname}")
-        wall, kms = timed_run(g, args.steps, args.warmup, torch)
         K = cfg.get("fuse", 1) if cfg.get("kernel") == 2 else 1
+        wall, kms = timed_run(g, args.steps, args.warmup, torch, K)
         per_node = (2 * 9 * c) if kw["populations"] else (2 * 3 * c)     # state bytes per node
         alg = per_node * lups                                          # read + write per launch
         rows[name] = dict(kernel=kname, mlups=round(lups * args.steps / wall / 1e6, 1),
@@ -455,7 +460,7 @@ def run_drop(args, torch):
             g = Grid(L, L, prec=st, periodic=3, multiphase=G, **kw)
             g.set_geometry(None, rho, z, z)
             if not kw:
-                g.autotune(steps=10, reps=2)
+                g.autotune(steps=30, reps=3)
             wall, kms = timed_run(g, steps, min(100, steps // 4), torch)
             dd = g.reduce()
             opts = g.options & ~C.OPT_SNAPSHOT

@@ -289,13 +289,15 @@ lbt1_kernel_config heuristic_config(int prec, bool haswall, int wall, int nx, in
   if (!haswall) {
     // several steps per pass (measured fastest on large periodic grids): FP32 three
     // steps at 4 columns per lane; FP64 two at 2 (registers); 16-bit storage two at
-    // 2 columns and tall strips (arithmetic-bound, so fewer redundant halo rows)
+    // 2 columns. Tall strips where there are enough of them: these kernels are
+    // bound by arithmetic, and a taller strip repeats fewer halo rows.
     const bool half = prec == LBT1_F16S || prec == LBT1_BF16S;
     const int v = prec == LBT1_F32 ? 4 : 2;
     const int k = prec == LBT1_F32 ? 3 : 2;
     if (nx % v == 0 && 62 * v <= std::max(62, nx)) {
-      const long tall = (long)((nx / v + 61) / 62) * ((ny + 29) / 30);
-      const int r = half ? (tall >= 8L * cus ? 30 : 6) : (prec == LBT1_F32 ? 14 : 6);
+      const long sx = (nx / v + 61) / 62;
+      const int r = half ? (sx * ((ny + 29) / 30) >= 8L * cus ? 30 : 6)
+                         : prec == LBT1_F32 ? (sx * ((ny + 21) / 22) >= 8L * cus ? 22 : 14) : 6;
       if (find_kernel(prec, false, 0, KIND_STRIP, v, r, k, false)) {
         c.vec = v;
         c.rows = r;
@@ -324,6 +326,7 @@ lbt1_status bind_config(lbt1_grid *g, const lbt1_kernel_config &want, int cus) {
     const StepKernel *k = find_kernel(g->prec, g->haswall, g->wall, KIND_BGK, 0, 0, 1, g->mp);
     if (!k) return fail(LBT1_EINVAL, "no built population kernel at this precision");
     g->kern = g->kern1 = k;
+    g->kern2 = nullptr;
     g->cfg = lbt1_kernel_config{};
     g->cfg.kernel = LBT1_KERNEL_GATHER;
     g->cfg.fuse = 1;
@@ -339,9 +342,10 @@ lbt1_status bind_config(lbt1_grid *g, const lbt1_kernel_config &want, int cus) {
     auto it = g_tuned.find(tune_key(g));
     c = it != g_tuned.end() ? it->second : heuristic_config(g->prec, g->haswall, g->wall, g->nx, g->ny, cus, g->mp);
   }
-  const StepKernel *k = nullptr, *k1 = nullptr;
+  const StepKernel *k = nullptr, *k1 = nullptr, *k2 = nullptr;
   if (c.kernel == LBT1_KERNEL_GATHER) {
     k = k1 = find_kernel(g->prec, g->haswall, g->wall, KIND_GATHER, 0, 0, 1, g->mp);
+    k2 = nullptr;
     c.vec = c.rows = c.waves = 0;
     c.fuse = 1;
   } else if (c.kernel == LBT1_KERNEL_STRIP) {
@@ -360,6 +364,9 @@ lbt1_status bind_config(lbt1_grid *g, const lbt1_kernel_config &want, int cus) {
     // a fused shape with no single-step strip of its height finishes odd step
     // counts with the gather kernel (same arithmetic, own launch shape)
     if (k && !k1 && c.fuse > 1) k1 = find_kernel(g->prec, g->haswall, g->wall, KIND_GATHER, 0, 0, 1, g->mp);
+    // three steps per launch: remainders of two steps take the two-step kernel of
+    // the same strip shape where one is built
+    if (c.fuse == 3) k2 = find_kernel(g->prec, g->haswall, g->wall, KIND_STRIP, c.vec, c.rows, 2, g->mp);
   } else {
     return fail(LBT1_EINVAL, "unknown kernel family %d", c.kernel);
   }
@@ -367,6 +374,7 @@ lbt1_status bind_config(lbt1_grid *g, const lbt1_kernel_config &want, int cus) {
     return fail(LBT1_EINVAL, "no built kernel for vec %d rows %d fuse %d at this precision", c.vec, c.rows, c.fuse);
   g->kern = k;
   g->kern1 = k1;
+  g->kern2 = k2;
   g->cfg = c;
   g->cfg.kernel = k->kind == KIND_GATHER ? LBT1_KERNEL_GATHER : LBT1_KERNEL_STRIP;
   if (k->kind == KIND_GATHER) {
@@ -563,10 +571,23 @@ lbt1_status enqueue_steps(lbt1_grid *g, int64_t n, hipStream_t s, bool use_graph
     }
   }
   const int K = g->kern->steps;
-  for (; n >= K; n -= K) {
+  // With a two-step companion the remainder after three-step launches is covered
+  // by two-step launches: one for 2 left, two for 1 left when the single-step
+  // companion is the (slower) gather kernel and at least 4 steps are asked for.
+  int64_t tail2 = 0;
+  if (g->kern2) {
+    if (n % K == 2) tail2 = 1;
+    if (n % K == 1 && n >= 4 && g->kern1->kind == KIND_GATHER) tail2 = 2;
+  }
+  for (; n - 2 * tail2 >= K; n -= K) {
     if ((e = launch_step(g, g->kern, g->parity, s)) != hipSuccess) return hip_fail(e, "step launch");
     g->parity ^= 1;
     g->steps += K;
+  }
+  for (; tail2 > 0; --tail2, n -= 2) {
+    if ((e = launch_step(g, g->kern2, g->parity, s)) != hipSuccess) return hip_fail(e, "step launch");
+    g->parity ^= 1;
+    g->steps += 2;
   }
   for (; n > 0; --n) {
     if ((e = launch_step(g, g->kern1, g->parity, s)) != hipSuccess) return hip_fail(e, "step launch");

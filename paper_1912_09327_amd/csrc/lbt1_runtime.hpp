@@ -79,6 +79,7 @@ struct lbt1_grid {
   bool user_cfg = false;
   const lbt1::StepKernel *kern = nullptr;   // advances kern->steps steps per launch
   const lbt1::StepKernel *kern1 = nullptr;  // single-step kernel of the same launch shape
+  const lbt1::StepKernel *kern2 = nullptr;  // two-step kernel of the same strip shape, when kern takes three
   lbt1::StripMap map{};
   dim3 grid{1, 1, 1}, block{1, 1, 1};
   dim3 grid1{1, 1, 1}, block1{1, 1, 1};  // launch shape of kern1

@@ -39,20 +39,20 @@ def test_fused_bitwise_equals_single_steps(prec, shape):
                     assert np.array_equal(a, b), (vec, rows, waves)
 
 
-@pytest.mark.parametrize("prec", ["f32", "f16s"])
-@pytest.mark.parametrize("vec,fuse", [(2, 2), (4, 3)])
-def test_fused_graph_bursts_and_splitting(prec, vec, fuse):
+@pytest.mark.parametrize("prec,vec,fuse,rows", [("f32", 2, 2, 14), ("f16s", 2, 2, 14), ("f32", 4, 3, 14),
+                                                ("f16s", 4, 3, 14), ("f32", 4, 3, 22)])
+def test_fused_graph_bursts_and_splitting(prec, vec, fuse, rows):
     """Bursts (32 launches of two steps; 21 launches of three, which flip the parity),
-    odd remainders and split calls."""
+    remainders (two-step launches after three-step ones, single steps) and split calls."""
     from paper_1912_09327_amd.grid import Grid
     nx, ny = 372, 90
     rho, jx, jy = _state(nx, ny, 5)
-    ref = gpu_run(None, rho, jx, jy, 217, prec, "paper", 3, kernel=dict(kernel="gather"))
+    ref = gpu_run(None, rho, jx, jy, 231, prec, "paper", 3, kernel=dict(kernel="gather"))
     g = Grid(nx, ny, prec=prec, periodic=3)
     try:
         g.set_geometry(None, rho, jx, jy)
-        g.set_kernel("strip", vec=vec, rows=14, waves=0, fuse=fuse)
-        for n in (1, 64, 3, 128, 21):
+        g.set_kernel("strip", vec=vec, rows=rows, waves=0, fuse=fuse)
+        for n in (1, 64, 3, 128, 21, 2, 4, 5, 1, 2):
             g.step(n)
         got = g.read_moments()
     finally:
@@ -116,15 +116,18 @@ def test_fused_refused_where_it_does_not_apply():
         g.close()
 
 
-@pytest.mark.parametrize("prec,vec,rows", [("f32", 4, 22), ("f16s", 2, 22), ("f16s", 2, 30),
-                                           ("bf16s", 2, 30)])
+@pytest.mark.parametrize("prec,vec,rows,fuse", [("f32", 4, 22, 2), ("f16s", 2, 22, 2), ("f16s", 2, 30, 2),
+                                                ("bf16s", 2, 30, 2), ("f32", 4, 22, 3)])
 @pytest.mark.parametrize("shape", [(512, 77), (248, 33)])
-def test_tall_fused_strips_bitwise(prec, vec, rows, shape):
+def test_tall_fused_strips_bitwise(prec, vec, rows, fuse, shape):
+    """Strips taller than the single-step kernels: the remainder of 25 steps goes to
+    the gather kernel (after two-step launches) or to two two-step launches (after
+    three-step launches)."""
     nx, ny = shape
     rho, jx, jy = _state(nx, ny, 41)
     base = gpu_run(None, rho, jx, jy, 25, prec, "paper", 3, (1e-5, 0.0), kernel=dict(kernel="gather"))
     for waves in (0, 8):
         got = gpu_run(None, rho, jx, jy, 25, prec, "paper", 3, (1e-5, 0.0),
-                      kernel=dict(kernel="strip", vec=vec, rows=rows, waves=waves, fuse=2))
+                      kernel=dict(kernel="strip", vec=vec, rows=rows, waves=waves, fuse=fuse))
         for a, b in zip(base, got):
             assert np.array_equal(a, b), waves
