@@ -294,12 +294,29 @@ __global__ void __launch_bounds__(256) k_reduce3_partial(Reduce3Args a) {
   }
 }
 
+// one wavefront: lane l combines partial rows l, l + 64, ... in index order, then a
+// fixed butterfly over the lanes (slot 4 is a maximum, the others sums)
 __global__ void __launch_bounds__(64) k_reduce3_final(const double *partials, int nparts, double *out) {
-  const int m = threadIdx.x;
-  if (m < 8) {
-    double v = 0.0;
-    for (int b = 0; b < nparts; ++b) v = m == 4 ? __builtin_fmax(v, partials[b * 8 + m]) : v + partials[b * 8 + m];
-    out[m] = v;
+  const int l = threadIdx.x;
+  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int b = l; b < nparts; b += 64) {
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      const double x = partials[b * 8 + m];
+      acc[m] = m == 4 ? __builtin_fmax(acc[m], x) : acc[m] + x;
+    }
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      const double o = __shfl_xor(acc[m], off);
+      acc[m] = m == 4 ? __builtin_fmax(acc[m], o) : acc[m] + o;
+    }
+  }
+  if (l == 0) {
+#pragma unroll
+    for (int m = 0; m < 8; ++m) out[m] = acc[m];
   }
 }
 

@@ -137,6 +137,37 @@ __device__ __forceinline__ void sc_force(const C (&psi)[9], C G, C &fx, C &fy) {
 // Arrivals g[q] at a node (g[q] travelled along e_q, from x - e_q).  Grouped
 // by the source row: y-1 (q = 5, 2, 6), y (1, 0, 3), y+1 (8, 4, 7).  This
 // order is part of the contract between kernels: all of them use it.
+// ----------------------------------------------------------------- lane exchange
+// Neighbour values along the wavefront: lane_left(x) is lane l - 1's x,
+// lane_right(x) lane l + 1's.  Lanes 0 and 63 hold halo columns whose values are
+// never stored, so what they receive at the open end does not matter.
+// FP32 and FP64 kernels are bound by latency: they use the whole-wavefront DPP
+// shifts of this chip family (a VALU move, often folded into the add or
+// subtract that consumes it; the lane without a source reads zero).  16-bit
+// storage kernels are bound by VALU issue: their exchange stays on the LDS
+// permute path, which issues outside the VALU.
+constexpr int kDppWaveShl1 = 0x130;  // lane l reads lane l + 1
+constexpr int kDppWaveShr1 = 0x138;  // lane l reads lane l - 1
+template <int CTRL> __device__ __forceinline__ int dpp_shift(int x) {
+  return __builtin_amdgcn_mov_dpp(x, CTRL, 0xf, 0xf, true);
+}
+template <int CTRL> __device__ __forceinline__ float dpp_shift(float x) {
+  return __int_as_float(dpp_shift<CTRL>(__float_as_int(x)));
+}
+template <int CTRL> __device__ __forceinline__ double dpp_shift(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = dpp_shift<CTRL>((int)(b & 0xffffffffLL)), hi = dpp_shift<CTRL>((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <int P, typename X> __device__ __forceinline__ X lane_left(X x) {
+  if constexpr (sizeof(typename Traits<P>::S) == 2) return __shfl_up(x, 1);
+  else return dpp_shift<kDppWaveShr1>(x);
+}
+template <int P, typename X> __device__ __forceinline__ X lane_right(X x) {
+  if constexpr (sizeof(typename Traits<P>::S) == 2) return __shfl_down(x, 1);
+  else return dpp_shift<kDppWaveShl1>(x);
+}
+
 template <typename C> __device__ __forceinline__ C row_sum(C a, C b, C c) { return (a + b) + c; }
 template <typename C> __device__ __forceinline__ C row_dif(C a, C c) { return a - c; }
 template <typename C>

@@ -24,18 +24,24 @@
 
 namespace lbt1 {
 
+// Per column of a stage: the partial sums of the pending target row (the one
+// completed by the next source row) and the up-sums of the newest source row.
+// The finish step adds the up and level sums of a target first, so they are
+// combined as soon as the level sum is known: ps = up.s + lev.s, px = up.x +
+// lev.x; us keeps up.s alone for the y momentum.
 template <int P, int VEC>
 struct FusedStage {
   using C = typename Traits<P>::C;
-  ArrS<C, VEC> upA, upB, lev;
+  C ps[VEC], px[VEC], us[VEC];  // pending target row
+  C ns[VEC], nx[VEC];           // up-sums of the newest source row
 };
 
-// One source row into stage `st` (values already decoded and scaled; Fx, Fy
+// One source row j into stage `st` (values already decoded and scaled; Fx, Fy
 // the force of each source column).  When `emit_row` (the stage has seen two
-// earlier rows), the target row one above is completed into dn/jxn/jyn
-// (unscaled arithmetic values).
+// earlier rows), target row j - 1 is completed into dn/jxn/jyn (unscaled
+// arithmetic values); the same additions in the same order as finish().
 template <int P, int VEC>
-__device__ __forceinline__ void fused_feed(FusedStage<P, VEC> &st, const bool odd, const bool emit_row,
+__device__ __forceinline__ void fused_feed(FusedStage<P, VEC> &st, const bool emit_row,
                                            const typename Traits<P>::C (&d)[VEC],
                                            const typename Traits<P>::C (&jx)[VEC],
                                            const typename Traits<P>::C (&jy)[VEC],
@@ -46,35 +52,36 @@ __device__ __forceinline__ void fused_feed(FusedStage<P, VEC> &st, const bool od
   C f[VEC][9];
 #pragma unroll
   for (int v = 0; v < VEC; ++v) emit<C>(d[v], jx[v], jy[v], Fx[v], Fy[v], f[v]);
-  const C L1 = __shfl_up(f[VEC - 1][1], 1);
-  const C L5 = __shfl_up(f[VEC - 1][5], 1);
-  const C L8 = __shfl_up(f[VEC - 1][8], 1);
-  const C R3 = __shfl_down(f[0][3], 1);
-  const C R6 = __shfl_down(f[0][6], 1);
-  const C R7 = __shfl_down(f[0][7], 1);
-  ArrS<C, VEC> &up_old = odd ? st.upB : st.upA;
-  if (emit_row) {
-#pragma unroll
-    for (int v = 0; v < VEC; ++v) {
-      const C a8 = v > 0 ? f[v - 1][8] : L8;
-      const C a4 = f[v][4];
-      const C a7 = v < VEC - 1 ? f[v + 1][7] : R7;
-      finish<C>(up_old.s[v], up_old.x[v], st.lev.s[v], st.lev.x[v], row_sum(a8, a4, a7), row_dif(a8, a7), dn[v],
-                jxn[v], jyn[v]);
-    }
-  }
+  const C L1 = lane_left<P>(f[VEC - 1][1]);
+  const C L5 = lane_left<P>(f[VEC - 1][5]);
+  const C L8 = lane_left<P>(f[VEC - 1][8]);
+  const C R3 = lane_right<P>(f[0][3]);
+  const C R6 = lane_right<P>(f[0][6]);
+  const C R7 = lane_right<P>(f[0][7]);
 #pragma unroll
   for (int v = 0; v < VEC; ++v) {
-    const C a5 = v > 0 ? f[v - 1][5] : L5;
-    const C a2 = f[v][2];
-    const C a6 = v < VEC - 1 ? f[v + 1][6] : R6;
+    const C a8 = v > 0 ? f[v - 1][8] : L8;
+    const C a4 = f[v][4];
+    const C a7 = v < VEC - 1 ? f[v + 1][7] : R7;
+    if (emit_row) {
+      const C ds = row_sum(a8, a4, a7), dx = row_dif(a8, a7);
+      dn[v] = st.ps[v] + ds;
+      jxn[v] = st.px[v] + dx;
+      jyn[v] = st.us[v] - ds;
+    }
     const C a1 = v > 0 ? f[v - 1][1] : L1;
     const C a0 = f[v][0];
     const C a3 = v < VEC - 1 ? f[v + 1][3] : R3;
-    up_old.s[v] = row_sum(a5, a2, a6);
-    up_old.x[v] = row_dif(a5, a6);
-    st.lev.s[v] = row_sum(a1, a0, a3);
-    st.lev.x[v] = row_dif(a1, a3);
+    const C ls = row_sum(a1, a0, a3), lx = row_dif(a1, a3);
+    // target row j: up-sums of row j - 1 plus the level sums of row j
+    st.ps[v] = st.ns[v] + ls;
+    st.px[v] = st.nx[v] + lx;
+    st.us[v] = st.ns[v];
+    const C a5 = v > 0 ? f[v - 1][5] : L5;
+    const C a2 = f[v][2];
+    const C a6 = v < VEC - 1 ? f[v + 1][6] : R6;
+    st.ns[v] = row_sum(a5, a2, a6);
+    st.nx[v] = row_dif(a5, a6);
   }
 }
 
@@ -147,7 +154,7 @@ __device__ __forceinline__ void fused_body(const StepArgs &a, const int chunk0, 
     }
   };
 
-  FusedStage<P, VEC> stage[K];
+  FusedStage<P, VEC> stage[K] = {};
   constexpr int PF = kPrefetch;
   constexpr int NR = NY + 2 * K;
   Row ring[PF + 1];
@@ -165,7 +172,7 @@ __device__ __forceinline__ void fused_body(const StepArgs &a, const int chunk0, 
       const int j = i - 2 * s;  // index of the row entering stage s
       if (j >= 0) {
         C dn[VEC], jxn[VEC], jyn[VEC];
-        fused_feed<P, VEC>(stage[s], (j & 1) != 0, j >= 2, d, jx, jy, Fx, Fy, dn, jxn, jyn);
+        fused_feed<P, VEC>(stage[s], j >= 2, d, jx, jy, Fx, Fy, dn, jxn, jyn);
         if (j < 2) break;  // nothing leaves stage s yet, so later stages get nothing
         SP out[3];
         encode(dn, jxn, jyn, out);

@@ -8,13 +8,30 @@
 
 namespace lbt1 {
 
-// one block: combine `nparts` partial rows in index order into out[6]
+// one wavefront: lane l combines partial rows l, l + 64, ... in index order, then
+// a fixed butterfly over the lanes; lane 0 writes out[6] (slot 3 is a maximum, the
+// others sums)
 __global__ void __launch_bounds__(64) k_reduce_final(const double *partials, int nparts, double *out) {
-  const int q = threadIdx.x;
-  if (q < 6) {
-    double v = 0.0;
-    for (int b = 0; b < nparts; ++b) v = q == 3 ? __builtin_fmax(v, partials[b * 6 + q]) : v + partials[b * 6 + q];
-    out[q] = v;
+  const int l = threadIdx.x;
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  for (int b = l; b < nparts; b += 64) {
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      const double x = partials[b * 6 + q];
+      acc[q] = q == 3 ? __builtin_fmax(acc[q], x) : acc[q] + x;
+    }
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      const double o = __shfl_xor(acc[q], off);
+      acc[q] = q == 3 ? __builtin_fmax(acc[q], o) : acc[q] + o;
+    }
+  }
+  if (l == 0) {
+#pragma unroll
+    for (int q = 0; q < 6; ++q) out[q] = acc[q];
   }
 }
 

@@ -164,13 +164,13 @@ __device__ __forceinline__ void sc_strip_body(const StepArgs &a, const int chunk
       o.jy[v] = jy;
       o.psi[v] = sc_psi<C>(C(1) + d, rho0, irho0);
     }
-    o.psiL = __shfl_up(o.psi[VEC - 1], 1);
-    o.psiR = __shfl_down(o.psi[0], 1);
+    o.psiL = lane_left<P>(o.psi[VEC - 1]);
+    o.psiR = lane_right<P>(o.psi[0]);
   };
   auto left = [](const Dec &r, int v) -> C { return v > 0 ? r.psi[v - 1] : r.psiL; };
   auto right = [](const Dec &r, int v) -> C { return v < VEC - 1 ? r.psi[v + 1] : r.psiR; };
 
-  FusedStage<P, VEC> st;
+  FusedStage<P, VEC> st = {};
   Dec dec[3];
   constexpr int PF = kPrefetch;
   constexpr int NR = NY + 4;
@@ -205,7 +205,7 @@ __device__ __forceinline__ void sc_strip_body(const StepArgs &a, const int chunk
     }
     const int j = i - 2;  // index of the source row entering the emission stage
     C dn[VEC], jxn[VEC], jyn[VEC];
-    fused_feed<P, VEC>(st, (j & 1) != 0, j >= 2, mid.d, mid.jx, mid.jy, Fx, Fy, dn, jxn, jyn);
+    fused_feed<P, VEC>(st, j >= 2, mid.d, mid.jx, mid.jy, Fx, Fy, dn, jxn, jyn);
     if (j < 2) continue;
     SP out[3];
 #pragma unroll

@@ -203,16 +203,16 @@ __device__ __forceinline__ void strip_body(const StepArgs &a, const int chunk0, 
     (void)fbits;
     // neighbour-lane emissions: heading +x from the lane on the left, -x from
     // the right (lanes 0 and 63 receive nothing useful; they write nothing)
-    const C L1 = __shfl_up(f[VEC - 1][1], 1);
-    const C L5 = __shfl_up(f[VEC - 1][5], 1);
-    const C L8 = __shfl_up(f[VEC - 1][8], 1);
-    const C R3 = __shfl_down(f[0][3], 1);
-    const C R6 = __shfl_down(f[0][6], 1);
-    const C R7 = __shfl_down(f[0][7], 1);
+    const C L1 = lane_left<P>(f[VEC - 1][1]);
+    const C L5 = lane_left<P>(f[VEC - 1][5]);
+    const C L8 = lane_left<P>(f[VEC - 1][8]);
+    const C R3 = lane_right<P>(f[0][3]);
+    const C R6 = lane_right<P>(f[0][6]);
+    const C R7 = lane_right<P>(f[0][7]);
     int Ls = 0, Rs = 0;
     if (HASWALL) {
-      Ls = __shfl_up((int)((sbits >> (VEC - 1)) & 1u), 1);
-      Rs = __shfl_down((int)(sbits & 1u), 1);
+      Ls = lane_left<P>((int)((sbits >> (VEC - 1)) & 1u));
+      Rs = lane_right<P>((int)(sbits & 1u));
     }
     // wall bits of the left / own / right source of column v
     auto bit_l = [&](int v) -> uint32_t { return v > 0 ? (sbits >> (v - 1)) & 1u : (uint32_t)Ls; };
@@ -552,20 +552,34 @@ __global__ void __launch_bounds__(256) k_reduce_batch(BatchReduceArgs b) {
   }
 }
 
-// The partials of each active grid, in item order, into out[slot * 6 + q].
+// The partials of each active grid (fixed order: lane-strided, then a butterfly)
+// into out[slot * 6 + q].
 __global__ void __launch_bounds__(64) k_reduce_batch_final(BatchReduceArgs b) {
   const int n = *b.nactive;
   for (int k = blockIdx.x; k < n; k += gridDim.x) {
     const int slot = b.active[k];
     const int2 r = b.ranges[slot];
-    const int q = threadIdx.x;
-    if (q < 6) {
-      double v = 0.0;
-      for (int i = 0; i < r.y; ++i) {
+    // lane l: partial rows l, l + 64, ... of the grid in order, then a fixed butterfly
+    const int l = threadIdx.x;
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (int i = l; i < r.y; i += 64) {
+#pragma unroll
+      for (int q = 0; q < 6; ++q) {
         const double x = b.partials[(long)(r.x + i) * 6 + q];
-        v = q == 3 ? __builtin_fmax(v, x) : v + x;
+        acc[q] = q == 3 ? __builtin_fmax(acc[q], x) : acc[q] + x;
       }
-      b.out[slot * 6 + q] = v;
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+#pragma unroll
+      for (int q = 0; q < 6; ++q) {
+        const double o = __shfl_xor(acc[q], off);
+        acc[q] = q == 3 ? __builtin_fmax(acc[q], o) : acc[q] + o;
+      }
+    }
+    if (l == 0) {
+#pragma unroll
+      for (int q = 0; q < 6; ++q) b.out[slot * 6 + q] = acc[q];
     }
   }
 }
