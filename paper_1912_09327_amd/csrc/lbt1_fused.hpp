@@ -155,21 +155,28 @@ __device__ __forceinline__ void fused_body(const StepArgs &a, const int chunk0, 
   };
 
   FusedStage<P, VEC> stage[K] = {};
-  constexpr int PF = kPrefetch;
+  // Two steps: one wavefront per SIMD is enough registers for a ring of rows
+  // loaded two ahead.  Three steps: the kernel is built for two wavefronts per
+  // SIMD (the other wavefront hides the load latency), which leaves no room for
+  // a prefetch ring; each row is loaded as it is needed.
+  constexpr int PF = K >= 3 ? 0 : kPrefetch;
   constexpr int NR = NY + 2 * K;
   Row ring[PF + 1];
 #pragma unroll
   for (int i = 0; i < PF; ++i) load_row(i, ring[i]);
-#pragma unroll
+#pragma clang loop unroll(full)
   for (int i = 0; i < NR; ++i) {
     if (i + PF < NR) load_row(i + PF, ring[(i + PF) % (PF + 1)]);
-    __builtin_amdgcn_sched_barrier(0);
+    if (PF > 0) __builtin_amdgcn_sched_barrier(0);
     C d[VEC], jx[VEC], jy[VEC];
     decode(ring[i % (PF + 1)].raw, d, jx, jy);
     // stage s receives its (i - 2s)-th row at iteration i
 #pragma unroll
     for (int s = 0; s < K; ++s) {
       const int j = i - 2 * s;  // index of the row entering stage s
+      // three steps: one stage at a time, so the stages' temporaries are not
+      // live together
+      if (K >= 3) __builtin_amdgcn_sched_barrier(0);
       if (j >= 0) {
         C dn[VEC], jxn[VEC], jyn[VEC];
         fused_feed<P, VEC>(stage[s], j >= 2, d, jx, jy, Fx, Fy, dn, jxn, jyn);
@@ -194,9 +201,13 @@ __device__ __forceinline__ void fused_body(const StepArgs &a, const int chunk0, 
 }
 
 template <int P, int VEC, int NY, int K>
-__global__ void __launch_bounds__(256) k_step_fused(StepArgs a, StripMap m) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(K >= 3 ? 2 : 1)))
+k_step_fused(StepArgs a, StripMap m) {
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  // three steps: the wavefront index read as a wave-uniform value keeps the
+  // strip coordinates and their divisions in scalar registers (the vector
+  // registers are all taken at two wavefronts per SIMD)
+  const int wave = K >= 3 ? __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) : (int)(threadIdx.x >> 6);
   const int xcd = blockIdx.x & 7;
   const int local = blockIdx.x >> 3;
   const int begin = xcd * m.per_xcd;

@@ -76,14 +76,13 @@ static const StepKernel kTable[] = {
     STRIP_ROWS(P_F32, 4),  STRIP_ROWS(P_F16S, 1), STRIP_ROWS(P_F16S, 2), STRIP_ROWS(P_F16S, 4),
     STRIP_ROWS_NOWALL(P_F16S, 8), STRIP_ROWS(P_BF16S, 1), STRIP_ROWS(P_BF16S, 2), STRIP_ROWS(P_BF16S, 4),
     STRIP_ROWS_NOWALL(P_BF16S, 8),
-    // two steps per launch, and three at 4 columns per lane (FP64 would need
-    // scratch memory); four would need more registers than a wavefront has
-    FUSED_ROWS(P_F32, 4, 3),   FUSED_ROWS(P_F16S, 4, 3),
+    // two steps per launch, and three for FP32 at 4 columns per lane (built for
+    // two wavefronts per SIMD: FP64, and 16-bit storage with its codec, would
+    // need scratch memory); four would need more registers than a wavefront has
+    FUSED_ROWS(P_F32, 4, 3),
     // taller strips: fewer redundant halo rows per stored row (FP32 at 30 rows
-    // would need scratch memory; 16-bit storage at three steps measured slower
-    // than at two, so only its short strips are kept)
-    FUSED(P_F32, 4, 22, 3),
-    FUSED(P_F32, 4, 22, 2),    FUSED_TALL(P_F16S, 2, 2),  FUSED_TALL(P_BF16S, 2, 2),
+    // measured slower than at 22)
+    FUSED(P_F32, 4, 22, 3),    FUSED(P_F32, 4, 22, 2),    FUSED_TALL(P_F16S, 2, 2),  FUSED_TALL(P_BF16S, 2, 2),
     FUSED_ROWS(P_F64, 2, 2),   FUSED_ROWS(P_F32, 2, 2),   FUSED_ROWS(P_F32, 4, 2),
     FUSED_ROWS(P_F16S, 2, 2),  FUSED_ROWS(P_F16S, 4, 2),  FUSED_ROWS(P_BF16S, 2, 2),
     FUSED_ROWS(P_BF16S, 4, 2),

@@ -302,7 +302,7 @@ lbt1_kernel_config heuristic_config(int prec, bool haswall, int wall, int nx, in
         c.vec = v;
         c.rows = r;
         c.fuse = k;
-        c.waves = prec == LBT1_F32 ? 8 : 0;
+        c.waves = 0;
         return c;
       }
     }
