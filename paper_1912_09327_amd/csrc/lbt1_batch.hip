@@ -80,14 +80,18 @@ namespace lbt1 {
 
 static const int kVecOfClass[4] = {1, 2, 4, 8};
 
-static int vec_class_for(int prec, int nx) {
+// Widest class whose chunk fits the grid: v divides nx, or x is not periodic
+// (the last chunk of a row then runs into the row padding, whose flags are
+// SOLID; pitch is nx rounded up to 64, a multiple of v).
+static int vec_class_for(int prec, int nx, bool periodic_x) {
   const int maxc = prec == LBT1_F64 ? 1 : 2;  // the batched kernels go up to 4 columns per lane
   for (int c = maxc; c >= 0; --c) {
     const int v = kVecOfClass[c];
-    if (nx % v == 0 && 64 * v <= std::max(64, nx)) return c;
+    if ((nx % v == 0 || !periodic_x) && 64 * v <= std::max(64, nx)) return c;
   }
   return 0;
 }
+static int chunks_of(int nx, int v) { return (nx + v - 1) / v; }
 
 // Launch size of a class: as many 256-thread blocks as the kernel's register
 // use lets every CU hold at once, but no more than the class has work items
@@ -113,7 +117,7 @@ static void rebuild_items(lbt1_batch *b) {
     const Slot &sl = b->slots[s];
     if (sl.state == LBT1_SLOT_FREE) continue;
     const int v = kVecOfClass[sl.vclass];
-    tall[sl.vclass] += (long)((sl.g->nx / v + 61) / 62) * ((sl.g->ny + 13) / 14);
+    tall[sl.vclass] += (long)((chunks_of(sl.g->nx, v) + 61) / 62) * ((sl.g->ny + 13) / 14);
   }
   for (int c = 0; c < 4; ++c) {
     b->items[c].clear();
@@ -127,7 +131,7 @@ static void rebuild_items(lbt1_batch *b) {
     if (sl.state == LBT1_SLOT_FREE) continue;
     const int v = kVecOfClass[sl.vclass];
     const int rows = b->rows[sl.vclass];
-    const int sx = (sl.g->nx / v + 61) / 62;  // strips of 62 chunks of v columns
+    const int sx = (chunks_of(sl.g->nx, v) + 61) / 62;  // strips of 62 chunks of v columns
     const int sy = (sl.g->ny + rows - 1) / rows;
     for (int k = 0; k < sx * sy; ++k) b->items[sl.vclass].push_back(make_int2(s, k));
     const long nodes = (long)sl.g->nx * sl.g->ny;
@@ -329,6 +333,9 @@ lbt1_status lbt1_batch_admit(lbt1_batch *b, lbt1_grid *g, int64_t step_budget, d
   if (!g->snap[0]) return fail(LBT1_EINVAL, "batched grids need LBT1_OPT_SNAPSHOT");
   if (g->device != b->device) return fail(LBT1_EINVAL, "grid is on another device");
   if (b->prec >= 0 && g->prec != b->prec) return fail(LBT1_EINVAL, "batch precision is %d, grid has %d", b->prec, g->prec);
+  const int vclass = vec_class_for(g->prec, g->nx, g->periodic & 1u);
+  if ((long)chunks_of(g->nx, kVecOfClass[vclass]) * kVecOfClass[vclass] > g->L.pitch)
+    return fail(LBT1_EINVAL, "batch: %d-column chunks overrun the row pitch %d", kVecOfClass[vclass], g->L.pitch);
   const size_t bytes = g->L.total;
   if (b->used + bytes > b->budget) return fail(LBT1_EBUSY, "HBM budget: %zu used + %zu > %zu", b->used, bytes, b->budget);
   int s = -1;
@@ -348,7 +355,7 @@ lbt1_status lbt1_batch_admit(lbt1_batch *b, lbt1_grid *g, int64_t step_budget, d
   sl.tol = residual_tol;
   sl.state = step_budget > 0 ? LBT1_SLOT_RUNNING : LBT1_SLOT_BUDGET;
   sl.bytes = bytes;
-  sl.vclass = vec_class_for(g->prec, g->nx);
+  sl.vclass = vclass;
   b->prec = g->prec;
   b->used += bytes;
   g->batch = b;
@@ -365,7 +372,7 @@ lbt1_status lbt1_batch_admit(lbt1_batch *b, lbt1_grid *g, int64_t step_budget, d
   d.wall = g->wall;
   d.parity0 = g->parity;
   d.steps_left = 0;
-  d.strips_x = (g->nx / kVecOfClass[sl.vclass] + 61) / 62;
+  d.strips_x = (chunks_of(g->nx, kVecOfClass[sl.vclass]) + 61) / 62;
   d.fx = g->F[0];
   d.fy = g->F[1];
   d.sc_d = g->sc[0];

@@ -235,7 +235,12 @@ lbt1_status check_device(int *dev_out, int *cus) {
 }
 
 // ----------------------------------------------------------------- kernel selection
-static bool strip_fits(int nx, int vec) { return vec >= 1 && nx % vec == 0; }
+// A strip kernel with vec columns per lane fits a grid when vec divides nx, or
+// when x is not periodic: then the last chunk of a row runs past nx into the
+// row padding (pitch is nx rounded up to 64, a multiple of vec), whose flags
+// are SOLID, exactly like the outside of a non-periodic axis.
+static bool strip_fits(int nx, int vec, bool periodic_x) { return vec >= 1 && (nx % vec == 0 || !periodic_x); }
+static int chunks_of(int nx, int vec) { return (nx + vec - 1) / vec; }
 
 const StepKernel *find_kernel(int prec, bool haswall, int wall, int kind, int vec, int rows, int fuse, bool sc) {
   int n = 0;
@@ -259,11 +264,11 @@ static std::tuple<int, int, int, int, int> tune_key(const lbt1_grid *g) {
 }
 
 // Default without a tuned entry: the gather kernel for tiny grids, else the
-// widest built strip kernel whose chunk divides nx and whose strip is not much
+// widest built strip kernel that fits nx (see strip_fits) and whose strip is not much
 // wider than the grid, with short strips (6 rows) when tall ones would not give
 // every CU several wavefronts (a strip's rows are walked one after another, so
 // its length sets the latency of a step).
-lbt1_kernel_config heuristic_config(int prec, bool haswall, int wall, int nx, int ny, int cus, bool sc) {
+lbt1_kernel_config heuristic_config(int prec, bool haswall, int wall, int nx, int ny, int cus, bool sc, bool px) {
   lbt1_kernel_config c{};
   if ((long)nx * ny < 64 * 64) {
     c.kernel = LBT1_KERNEL_GATHER;
@@ -309,12 +314,12 @@ lbt1_kernel_config heuristic_config(int prec, bool haswall, int wall, int nx, in
   }
   const int cands[] = {8, 4, 2, 1};
   for (int v : cands) {
-    if (nx % v == 0 && 62 * v <= std::max(62, nx) && find_kernel(prec, haswall, wall, KIND_STRIP, v, 14, 1, false)) {
+    if (strip_fits(nx, v, px) && 62 * v <= std::max(62, nx) && find_kernel(prec, haswall, wall, KIND_STRIP, v, 14, 1, false)) {
       c.vec = v;
       break;
     }
   }
-  const long tall = (long)((nx / c.vec + 61) / 62) * ((ny + 13) / 14);
+  const long tall = (long)((chunks_of(nx, c.vec) + 61) / 62) * ((ny + 13) / 14);
   c.rows = tall < 8L * cus ? 6 : 14;
   return c;
 }
@@ -340,7 +345,7 @@ lbt1_status bind_config(lbt1_grid *g, const lbt1_kernel_config &want, int cus) {
   if (c.kernel == LBT1_KERNEL_AUTO) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tuned.find(tune_key(g));
-    c = it != g_tuned.end() ? it->second : heuristic_config(g->prec, g->haswall, g->wall, g->nx, g->ny, cus, g->mp);
+    c = it != g_tuned.end() ? it->second : heuristic_config(g->prec, g->haswall, g->wall, g->nx, g->ny, cus, g->mp, g->periodic & 1u);
   }
   const StepKernel *k = nullptr, *k1 = nullptr, *k2 = nullptr;
   if (c.kernel == LBT1_KERNEL_GATHER) {
@@ -349,8 +354,10 @@ lbt1_status bind_config(lbt1_grid *g, const lbt1_kernel_config &want, int cus) {
     c.vec = c.rows = c.waves = 0;
     c.fuse = 1;
   } else if (c.kernel == LBT1_KERNEL_STRIP) {
-    if (!strip_fits(g->nx, c.vec))
-      return fail(LBT1_EINVAL, "strip kernel: vec %d does not divide nx %d", c.vec, g->nx);
+    if (!strip_fits(g->nx, c.vec, g->periodic & 1u))
+      return fail(LBT1_EINVAL, "strip kernel: vec %d does not divide nx %d on a grid periodic in x", c.vec, g->nx);
+    if ((long)chunks_of(g->nx, c.vec) * c.vec > g->L.pitch)
+      return fail(LBT1_EINVAL, "strip kernel: vec %d chunks overrun the row pitch %d", c.vec, g->L.pitch);
     if (c.waves < 0 || c.waves > 32) return fail(LBT1_EINVAL, "waves %d out of range", c.waves);
     if (c.fuse == 0) c.fuse = 1;
     if (c.fuse < 1 || c.fuse > c.vec) return fail(LBT1_EINVAL, "fuse %d must be between 1 and vec %d", c.fuse, c.vec);
@@ -382,7 +389,7 @@ lbt1_status bind_config(lbt1_grid *g, const lbt1_kernel_config &want, int cus) {
     g->grid = dim3((g->nx + 63) / 64, (g->ny + 3) / 4, 1);
   } else {
     StripMap &m = g->map;
-    m.strips_x = (g->nx / c.vec + 61) / 62;  // 62 chunks of vec columns per strip
+    m.strips_x = (chunks_of(g->nx, c.vec) + 61) / 62;  // 62 chunks of vec columns per strip
     m.strips_y = (g->ny + c.rows - 1) / c.rows;
     const int strips = m.strips_x * m.strips_y;
     m.units = (strips + 3) / 4;
@@ -1170,7 +1177,7 @@ lbt1_status lbt1_autotune(lbt1_grid *g, int32_t steps, int32_t reps, lbt1_kernel
     for (int r : rows)
       for (int w : waves)
         for (int f : fuses) {
-          if (!strip_fits(g->nx, v)) continue;
+          if (!strip_fits(g->nx, v, g->periodic & 1u)) continue;
           if (f > 1 && (g->haswall || g->mp)) continue;
           if (g->mp && g->haswall) continue;
           if (!find_kernel(g->prec, g->haswall, g->wall, KIND_STRIP, v, r, f, g->mp)) continue;

@@ -126,7 +126,9 @@ __device__ __forceinline__ void strip_body(const StepArgs &a, const int chunk0, 
   S *__restrict__ d0p = static_cast<S *>(a.dst[0]);
   S *__restrict__ d1p = static_cast<S *>(a.dst[1]);
   S *__restrict__ d2p = static_cast<S *>(a.dst[2]);
-  const int nch = a.nx / VEC;  // VEC divides nx
+  // chunks per row: VEC divides nx when x is periodic; otherwise the last chunk
+  // may run into the row padding, whose flags are SOLID (pitch is a multiple of 64)
+  const int nch = (a.nx + VEC - 1) / VEC;
   const int ch = chunk0 - 1 + lane;
   // source chunk: wrapped when x is periodic; outside a non-periodic x it is a wall
   bool col_ok = true;

@@ -29,9 +29,11 @@ def _grid(spec, prec):
     return g, (flags, rho, jx, jy, per, F)
 
 
+# odd widths 147 and 261 are not periodic in x: their strips take 2 and 4 columns
+# per lane with the last chunk of a row running into the (SOLID) row padding
 SPECS = [("cavity", 37, 0.08), ("cavity", 64, 0.05), ("channel", 96, 0.8), ("cavity", 130, 0.1),
-         ("channel", 200, 0.7), ("cavity", 256, 0.03)]
-BUDGETS = [130, 250, 75, 300, 260, 190]
+         ("channel", 200, 0.7), ("cavity", 256, 0.03), ("cavity", 147, 0.07), ("cavity", 261, 0.05)]
+BUDGETS = [130, 250, 75, 300, 260, 190, 121, 97]
 
 
 @pytest.mark.parametrize("prec", ["f32", "f16s", "bf16s"])
@@ -59,6 +61,7 @@ def test_batch_alone_vs_mix_bitwise(prec):
         from paper_1912_09327_amd.grid import Grid
         h = Grid(flags.shape[1], flags.shape[0], prec=prec, periodic=per, force=F)
         h.set_geometry(flags, rho, jx, jy)
+        h.set_kernel("gather")           # one thread per node: no chunks, no padding
         h.step(budget)
         alone = h.read_moments()
         h.close()

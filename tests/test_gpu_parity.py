@@ -100,6 +100,50 @@ def test_kernel_families_are_bitwise_identical(prec, kind):
                     assert np.array_equal(a, b), (vec, rows, waves)
 
 
+# Widths no wider chunk divides (131, 517), or 2 divides but 4 does not (250): on grids
+# not periodic in x the last chunk of a row runs into the row padding, whose flags
+# are SOLID, so strips of 2 and 4 columns per lane still apply.
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16s"])
+@pytest.mark.parametrize("kind", ["cavity", "open", "obstacles_walls"])
+@pytest.mark.parametrize("shape", [(131, 45), (517, 33), (250, 20)])
+def test_padded_last_chunk_bitwise(prec, kind, shape):
+    nx, ny = shape
+    if kind == "obstacles_walls":
+        rng = np.random.default_rng(nx + ny)
+        rho, jx, jy = I.random_state(nx, ny, rng)
+        flags, per = I.random_obstacles(nx, ny, 0.15, rng), 2      # walls at x = -1 and x = nx
+    else:
+        flags, rho, jx, jy, per = _case(kind, nx, ny, nx + ny)
+    F = (1e-5, -2e-5)
+    base = gpu_run(flags, rho, jx, jy, 21, prec, "halfway", per, F, kernel=GATHER)
+    for vec in ((2,) if prec == "f64" else (2, 4)):
+        for rows in (6, 14):
+            got = gpu_run(flags, rho, jx, jy, 21, prec, "halfway", per, F, kernel=strip(vec, rows))
+            for a, b in zip(base, got):
+                assert np.array_equal(a, b), (vec, rows)
+    if prec == "f64":
+        ref = oracle_run(flags, rho, jx, jy, 21, "halfway", per, F)
+        ex, ej = field_errors(base, ref, flags, (rho, jx, jy))
+        assert ex <= TOL["f64"] and ej <= JTOL["f64"], (ex, ej)
+
+
+def test_padded_chunk_refused_when_x_is_periodic():
+    from paper_1912_09327_amd import _capi as C
+    from paper_1912_09327_amd.grid import Grid
+    flags, per = I.channel(131, 20)                 # periodic in x, odd width
+    g = Grid(131, 20, prec="f32", periodic=per)
+    try:
+        g.set_geometry(flags)
+        for vec in (2, 4):
+            with pytest.raises(C.Lbt1Error) as e:
+                g.set_kernel("strip", vec=vec, rows=14)
+            assert e.value.status == C.EINVAL
+        g.set_kernel("strip", vec=1, rows=14)
+        g.step(2)
+    finally:
+        g.close()
+
+
 @pytest.mark.parametrize("prec", ["f16s", "bf16s"])
 @pytest.mark.parametrize("kind", ["periodic", "cavity"])
 def test_reduced_precision_within_stated_bar(prec, kind):
