@@ -131,6 +131,34 @@ def copy_ceiling(nbytes=2 << 30):
     return C.probe_bandwidth(C.PROBE_COPY, nbytes, nontemporal=False, reps=3)
 
 
+# Vector-ALU issue ceiling: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (one wave64 VALU
+# instruction per SIMD every 4 cycles), in T lane-operations/s.  Operations per update
+# in the kernel expression: emission 32 and target sums 14; the 16-bit storage codec
+# adds about 12.
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+ALG_OPS_PER_LUP = {"f64": 46, "f32": 46, "f16s": 58, "bf16s": 58}
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("lbt1_step.hpp", "lbt1_fused.hpp", "lbt1_device.hpp", "lbt1_args.hpp", "lbt1_kernels.hip"):
+        h.update(open(os.path.join(ROOT, "paper_1912_09327_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_valu(storage, kernel_name):
+    """Vector-ALU lane operations per launch of the step kernel from the committed
+    rocprofv3 summary (profiles/valu_periodic8192.json: SQ_INSTS_VALU per dispatch
+    times 64 lanes), if it was taken on this kernel and these kernel sources."""
+    try:
+        rec = json.load(open(os.path.join(ROOT, "profiles", "valu_periodic8192.json")))[storage]
+    except (OSError, KeyError, ValueError):
+        return None
+    if rec.get("source_hash") != kernel_source_hash() or rec.get("kernel_bench") != kernel_name:
+        return None
+    return rec["valu_per_dispatch"] * 64
+
+
 def measured_traffic(storage, kernel_name, kernel_ms):
     """HBM traffic of the step kernel from the committed rocprofv3 counter summary
     (profiles/traffic_periodic8192.json: FETCH_SIZE and WRITE_SIZE per dispatch, each
@@ -141,10 +169,7 @@ def measured_traffic(storage, kernel_name, kernel_ms):
         rec = json.load(open(path))[storage]
     except (OSError, KeyError, ValueError):
         return None
-    h = hashlib.sha256()
-    for f in ("lbt1_step.hpp", "lbt1_fused.hpp", "lbt1_device.hpp", "lbt1_args.hpp", "lbt1_kernels.hip"):
-        h.update(open(os.path.join(ROOT, "paper_1912_09327_amd", "csrc", f), "rb").read())
-    if rec.get("source_hash") != h.hexdigest()[:16] or rec.get("kernel_bench") != kernel_name:
+    if rec.get("source_hash") != kernel_source_hash() or rec.get("kernel_bench") != kernel_name:
         return None
     return dict(bytes_per_launch=rec["traffic_bytes"], ratio=rec["traffic_ratio"],
                 GBps=rec["traffic_bytes"] / (kernel_ms * 1e-3) / 1e9)
@@ -290,6 +315,20 @@ def run_periodic(args, torch):
         line["roofline"]["traffic"] = round(tr["GBps"], 1)
         line["roofline"]["traffic_bytes_per_launch"] = round(tr["bytes_per_launch"])
         line["roofline"]["traffic_over_algorithmic"] = round(tr["ratio"], 4)
+    # the fused kernels are close to the vector-ALU issue ceiling as well: operations per
+    # update from the kernel expression, and the VALU instructions rocprofv3 counted
+    lups_launch = lups * head["steps_per_launch"]
+    launch_s = head["kernel_ms"] * 1e-3
+    ops = ALG_OPS_PER_LUP[args.storage]
+    alu = {"achieved": round(ops * lups_launch / launch_s / 1e12, 2), "peak": round(VALU_PEAK_TOPS, 2),
+           "unit": "T lane-op/s", "frac": round(ops * lups_launch / launch_s / 1e12 / VALU_PEAK_TOPS, 4),
+           "ops_per_lup": ops, "counted": None}
+    counted = measured_valu(args.storage, head["kernel"])
+    if counted is not None:
+        alu["counted"] = round(counted / launch_s / 1e12, 2)
+        alu["counted_frac"] = round(counted / launch_s / 1e12 / VALU_PEAK_TOPS, 4)
+        alu["counted_ops_per_lup"] = round(counted / lups_launch, 2)
+    line["roofline"]["alu"] = alu
     try:
         cc = copy_ceiling()
         line["roofline"]["copy_ceiling_GBps"] = round(cc, 1)
