@@ -73,10 +73,11 @@ static const void *step3_kernel(int prec, int q, bool haswall, int wall) {
 }
 
 constexpr int kZChunk = 16;  // planes a tile block marches through
+constexpr int kTile3Y = 8;   // rows of a tile block (64 x 8 nodes, 512 threads)
 
 static const void *tile3_kernel(int prec, int q) {
 #define T3(P, Q) \
-  if (prec == P && q == Q) return (const void *)&k_step3_tile<P, Q, kZChunk>;
+  if (prec == P && q == Q) return (const void *)&k_step3_tile<P, Q, kZChunk, kTile3Y>;
   T3(P_F64, 19) T3(P_F64, 27) T3(P_F32, 19) T3(P_F32, 27) T3(P_F16S, 19) T3(P_F16S, 27) T3(P_BF16S, 19)
   T3(P_BF16S, 27)
 #undef T3
@@ -336,7 +337,7 @@ lbt1_status lbt1_grid3d_step(lbt1_grid3d *g, int64_t n) {
   if (!g->geometry) return fail(LBT1_ESTATE, "step before set_geometry");
   hipError_t e;
   if ((e = hipSetDevice(g->device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
-  const dim3 block = g->tile ? dim3(256, 1, 1) : dim3(64, 4, 1);
+  const dim3 block = g->tile ? dim3(64 * kTile3Y, 1, 1) : dim3(64, 4, 1);
   const dim3 grid = g->tile ? dim3((g->nx + kTile3X - 1) / kTile3X, (g->ny + kTile3Y - 1) / kTile3Y,
                                    (g->nz + kZChunk - 1) / kZChunk)
                             : dim3((g->nx + 63) / 64, (g->ny + 3) / 4, g->nz);

@@ -56,13 +56,47 @@ __device__ __forceinline__ C add_comp(C c, int e, C v) {
   return e == 1 ? c + v : e == -1 ? c - v : c;
 }
 
+// a += e * v for e in {-1, 0, 1}, where `have` says whether a holds a term yet:
+// the first term is taken as it is (a negation is exact), so no addition of
+// zero is issued.  With the direction loops unrolled, `have` is a compile-time
+// value.
+template <typename C>
+__device__ __forceinline__ void acc_comp(C &a, bool &have, int e, C v) {
+  if (e == 0) return;
+  if (have) {
+    a = add_comp<C>(a, e, v);
+  } else {
+    a = e > 0 ? v : -v;
+    have = true;
+  }
+}
+
+// e_q . J, formed from its nonzero components in x, y, z order (0 for the rest
+// direction)
+template <typename C>
+__device__ __forceinline__ C dot_e(int q, C Jx, C Jy, C Jz) {
+  C r = C(0);
+  bool have = false;
+  acc_comp<C>(r, have, k3x[q], Jx);
+  acc_comp<C>(r, have, k3y[q], Jy);
+  acc_comp<C>(r, have, k3z[q], Jz);
+  return r;
+}
+
+// Equilibrium deviation w_q [s (e.J)^2 + 3 e.J + b] with s = 4.5 / rho and
+// b = d - 1.5 |J|^2 / rho; for the rest direction (e = 0) it is w_0 b.
+template <typename C, int Q>
+__device__ __forceinline__ C emit3_sb(int q, C Jx, C Jy, C Jz, C s, C b) {
+  if (k3x[q] == 0 && k3y[q] == 0 && k3z[q] == 0) return C(w3<Q>(q)) * b;
+  const C eJ = dot_e<C>(q, Jx, Jy, Jz);
+  return C(w3<Q>(q)) * fmaC<C>(s, eJ * eJ, fmaC<C>(C(3), eJ, b));
+}
+
 // Equilibrium deviation a node with deviation d and forced momentum J sends
 // along e_q (inv = 1 / (1 + d), t = |J|^2 inv).
 template <typename C, int Q>
 __device__ __forceinline__ C emit3(int q, C d, C Jx, C Jy, C Jz, C inv, C t) {
-  const C eJ = add_comp<C>(add_comp<C>(add_comp<C>(C(0), k3x[q], Jx), k3y[q], Jy), k3z[q], Jz);
-  const C b = fmaC<C>(C(-1.5), t, d);
-  return C(w3<Q>(q)) * fmaC<C>(C(4.5) * inv, eJ * eJ, fmaC<C>(C(3), eJ, b));
+  return emit3_sb<C, Q>(q, Jx, Jy, Jz, C(4.5) * inv, fmaC<C>(C(-1.5), t, d));
 }
 
 template <int P>
@@ -106,6 +140,7 @@ __global__ void __launch_bounds__(256) k_step3_gather(Step3Args a) {
     own_t = (Jx * Jx + Jy * Jy + Jz * Jz) * own_inv;
   }
   C dn = C(0), xn = C(0), yn = C(0), zn = C(0);
+  bool hx = false, hy = false, hz = false;
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     const int sx = wrap_axis(x - k3x[q], a.nx, a.periodic & 1u);
@@ -126,10 +161,10 @@ __global__ void __launch_bounds__(256) k_step3_gather(Step3Args a) {
     } else {
       f = emit3<C, Q>(inv3<Q>(q), d0, jx0 + Fx, jy0 + Fy, jz0 + Fz, own_inv, own_t);
     }
-    dn += f;
-    xn = add_comp<C>(xn, k3x[q], f);
-    yn = add_comp<C>(yn, k3y[q], f);
-    zn = add_comp<C>(zn, k3z[q], f);
+    dn = q == 0 ? f : dn + f;
+    acc_comp<C>(xn, hx, k3x[q], f);
+    acc_comp<C>(yn, hy, k3y[q], f);
+    acc_comp<C>(zn, hz, k3z[q], f);
   }
   if (T::kScaled) {
     dn *= C(a.is_d);
@@ -143,46 +178,71 @@ __global__ void __launch_bounds__(256) k_step3_gather(Step3Args a) {
   static_cast<S *>(a.dst[3])[i] = T::enc(zn);
 }
 
-// Periodic grids without wall or fixed nodes: a block of 64 x 4 nodes marches
+// Periodic grids without wall or fixed nodes: a block of 64 x TY nodes marches
 // along z through ZC planes.  Three planes of its tile plus a one-node halo
 // live in LDS as the per-source values every emission needs (J, s = 4.5 / rho,
 // b = d - 1.5 |J|^2 / rho), computed once per node and plane; each target then
 // forms its Q arrivals from LDS.  The per-direction arithmetic is that of the
 // gather kernel, so the two give the same bits.
-constexpr int kTile3X = 64, kTile3Y = 4;
-constexpr int kHalo3X = kTile3X + 2, kHalo3Y = kTile3Y + 2, kHalo3N = kHalo3X * kHalo3Y;
+//
+// Loading a plane: every thread fills the LDS slot of its own node, and the
+// first 2 (64 + 2) + 2 TY threads each fill one halo-ring slot (the other
+// wavefronts skip that pass).  The in-plane offsets of both (wrapped, periodic
+// in x and y) do not depend on z and are computed once.
+constexpr int kTile3X = 64;
 
-template <int P, int Q, int ZC>
-__global__ void __launch_bounds__(256) k_step3_tile(Step3Args a) {
+template <int P, int Q, int ZC, int TY>
+__global__ void __launch_bounds__(64 * TY) k_step3_tile(Step3Args a) {
   using T = Traits<P>;
   using C = typename T::C;
   using S = typename T::S;
-  __shared__ C sJx[3][kHalo3N], sJy[3][kHalo3N], sJz[3][kHalo3N], sS[3][kHalo3N], sB[3][kHalo3N];
+  constexpr int HX = kTile3X + 2, HY = TY + 2, HN = HX * HY;
+  constexpr int RING = 2 * HX + 2 * TY;  // halo slots outside the tile
+  __shared__ C sJx[3][HN], sJy[3][HN], sJz[3][HN], sS[3][HN], sB[3][HN];
   const int tid = threadIdx.x;
   const int tx = tid & 63, ty = tid >> 6;
-  const int x0 = blockIdx.x * kTile3X, y0 = blockIdx.y * kTile3Y, z0 = blockIdx.z * ZC;
+  const int x0 = blockIdx.x * kTile3X, y0 = blockIdx.y * TY, z0 = blockIdx.z * ZC;
   const C Fx = C(a.fx), Fy = C(a.fy), Fz = C(a.fz);
-  // load plane z (wrapped) of the halo tile into LDS slot `slot`
-  auto load_plane = [&](int z, int slot) __attribute__((always_inline)) {
-    const int zz = wrap_axis(z, a.nz, true);
-#pragma unroll
-    for (int r = 0; r < 2; ++r) {
-      const int h = tid + r * 256;
-      if (h < kHalo3N) {
-        const int hx = h % kHalo3X, hy = h / kHalo3X;
-        const int gx = wrap_axis(x0 - 1 + hx, a.nx, true), gy = wrap_axis(y0 - 1 + hy, a.ny, true);
-        C d, jx, jy, jz;
-        load3<P>(a, (long)zz * a.zs + (long)gy * a.rs + gx, d, jx, jy, jz);
-        const C inv = recip<C>(C(1) + d);
-        const C Jx = jx + Fx, Jy = jy + Fy, Jz = jz + Fz;
-        const C t = (Jx * Jx + Jy * Jy + Jz * Jz) * inv;
-        sJx[slot][h] = Jx;
-        sJy[slot][h] = Jy;
-        sJz[slot][h] = Jz;
-        sS[slot][h] = C(4.5) * inv;
-        sB[slot][h] = fmaC<C>(C(-1.5), t, d);
-      }
+  const int own_h = (ty + 1) * HX + tx + 1;
+  const long own_off = (long)wrap_axis(y0 + ty, a.ny, true) * a.rs + wrap_axis(x0 + tx, a.nx, true);
+  const bool has_ring = tid < RING;
+  int ring_h = 0;
+  long ring_off = 0;
+  if (has_ring) {
+    int hx, hy;
+    if (tid < HX) {  // row below the tile
+      hx = tid;
+      hy = 0;
+    } else if (tid < 2 * HX) {  // row above
+      hx = tid - HX;
+      hy = HY - 1;
+    } else if (tid < 2 * HX + TY) {  // left column
+      hx = 0;
+      hy = 1 + (tid - 2 * HX);
+    } else {  // right column
+      hx = HX - 1;
+      hy = 1 + (tid - 2 * HX - TY);
     }
+    ring_h = hy * HX + hx;
+    ring_off = (long)wrap_axis(y0 - 1 + hy, a.ny, true) * a.rs + wrap_axis(x0 - 1 + hx, a.nx, true);
+  }
+  auto put = [&](const long i, const int slot, const int h) __attribute__((always_inline)) {
+    C d, jx, jy, jz;
+    load3<P>(a, i, d, jx, jy, jz);
+    const C inv = recip<C>(C(1) + d);
+    const C Jx = jx + Fx, Jy = jy + Fy, Jz = jz + Fz;
+    const C t = (Jx * Jx + Jy * Jy + Jz * Jz) * inv;
+    sJx[slot][h] = Jx;
+    sJy[slot][h] = Jy;
+    sJz[slot][h] = Jz;
+    sS[slot][h] = C(4.5) * inv;
+    sB[slot][h] = fmaC<C>(C(-1.5), t, d);
+  };
+  // plane z (wrapped) of the halo tile into LDS slot `slot`
+  auto load_plane = [&](const int z, const int slot) __attribute__((always_inline)) {
+    const long zo = (long)wrap_axis(z, a.nz, true) * a.zs;
+    put(zo + own_off, slot, own_h);
+    if (has_ring) put(zo + ring_off, slot, ring_h);
   };
   load_plane(z0 - 1, 0);
   load_plane(z0, 1);
@@ -195,17 +255,16 @@ __global__ void __launch_bounds__(256) k_step3_tile(Step3Args a) {
     __syncthreads();
     if (out) {
       C dn = C(0), xn = C(0), yn = C(0), zn = C(0);
+      bool hx = false, hy = false, hz = false;
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
         const int slot = (k + 1 - k3z[q] + 3) % 3;  // plane z - e_z
-        const int h = (ty + 1 - k3y[q]) * kHalo3X + (tx + 1 - k3x[q]);
-        const C Jx = sJx[slot][h], Jy = sJy[slot][h], Jz = sJz[slot][h];
-        const C eJ = add_comp<C>(add_comp<C>(add_comp<C>(C(0), k3x[q], Jx), k3y[q], Jy), k3z[q], Jz);
-        const C f = C(w3<Q>(q)) * fmaC<C>(sS[slot][h], eJ * eJ, fmaC<C>(C(3), eJ, sB[slot][h]));
-        dn += f;
-        xn = add_comp<C>(xn, k3x[q], f);
-        yn = add_comp<C>(yn, k3y[q], f);
-        zn = add_comp<C>(zn, k3z[q], f);
+        const int h = (ty + 1 - k3y[q]) * HX + (tx + 1 - k3x[q]);
+        const C f = emit3_sb<C, Q>(q, sJx[slot][h], sJy[slot][h], sJz[slot][h], sS[slot][h], sB[slot][h]);
+        dn = q == 0 ? f : dn + f;
+        acc_comp<C>(xn, hx, k3x[q], f);
+        acc_comp<C>(yn, hy, k3y[q], f);
+        acc_comp<C>(zn, hz, k3z[q], f);
       }
       if (T::kScaled) {
         dn *= C(a.is_d);
