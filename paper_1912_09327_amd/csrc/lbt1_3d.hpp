@@ -188,7 +188,8 @@ __global__ void __launch_bounds__(256) k_step3_gather(Step3Args a) {
 // Loading a plane: every thread fills the LDS slot of its own node, and the
 // first 2 (64 + 2) + 2 TY threads each fill one halo-ring slot (the other
 // wavefronts skip that pass).  The in-plane offsets of both (wrapped, periodic
-// in x and y) do not depend on z and are computed once.
+// in x and y) do not depend on z and are computed once; the moments of a plane
+// are loaded into registers one plane before they go to LDS.
 constexpr int kTile3X = 64;
 
 template <int P, int Q, int ZC, int TY>
@@ -226,9 +227,16 @@ __global__ void __launch_bounds__(64 * TY) k_step3_tile(Step3Args a) {
     ring_h = hy * HX + hx;
     ring_off = (long)wrap_axis(y0 - 1 + hy, a.ny, true) * a.rs + wrap_axis(x0 - 1 + hx, a.nx, true);
   }
-  auto put = [&](const long i, const int slot, const int h) __attribute__((always_inline)) {
-    C d, jx, jy, jz;
-    load3<P>(a, i, d, jx, jy, jz);
+  // plane loads run one plane ahead in registers: the loads of plane z + 2 are
+  // in flight while the targets of plane z are formed
+  C od, ojx, ojy, ojz, rd = C(0), rjx = C(0), rjy = C(0), rjz = C(0);
+  auto fetch = [&](const int z) __attribute__((always_inline)) {
+    const long zo = (long)wrap_axis(z, a.nz, true) * a.zs;
+    load3<P>(a, zo + own_off, od, ojx, ojy, ojz);
+    if (has_ring) load3<P>(a, zo + ring_off, rd, rjx, rjy, rjz);
+  };
+  auto put = [&](const C d, const C jx, const C jy, const C jz, const int slot, const int h)
+      __attribute__((always_inline)) {
     const C inv = recip<C>(C(1) + d);
     const C Jx = jx + Fx, Jy = jy + Fy, Jz = jz + Fz;
     const C t = (Jx * Jx + Jy * Jy + Jz * Jz) * inv;
@@ -238,20 +246,23 @@ __global__ void __launch_bounds__(64 * TY) k_step3_tile(Step3Args a) {
     sS[slot][h] = C(4.5) * inv;
     sB[slot][h] = fmaC<C>(C(-1.5), t, d);
   };
-  // plane z (wrapped) of the halo tile into LDS slot `slot`
-  auto load_plane = [&](const int z, const int slot) __attribute__((always_inline)) {
-    const long zo = (long)wrap_axis(z, a.nz, true) * a.zs;
-    put(zo + own_off, slot, own_h);
-    if (has_ring) put(zo + ring_off, slot, ring_h);
+  // the fetched plane into LDS slot `slot`
+  auto store_plane = [&](const int slot) __attribute__((always_inline)) {
+    put(od, ojx, ojy, ojz, slot, own_h);
+    if (has_ring) put(rd, rjx, rjy, rjz, slot, ring_h);
   };
-  load_plane(z0 - 1, 0);
-  load_plane(z0, 1);
+  fetch(z0 - 1);
+  store_plane(0);
+  fetch(z0);
+  store_plane(1);
+  fetch(z0 + 1);
   const int x = x0 + tx, y = y0 + ty;
   const bool out = x < a.nx && y < a.ny;
   for (int k = 0; k < ZC; ++k) {
     const int z = z0 + k;
     if (z >= a.nz) break;  // uniform across the block
-    load_plane(z + 1, (k + 2) % 3);
+    store_plane((k + 2) % 3);  // plane z + 1
+    if (k + 1 < ZC) fetch(z + 2);
     __syncthreads();
     if (out) {
       C dn = C(0), xn = C(0), yn = C(0), zn = C(0);
