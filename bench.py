@@ -67,6 +67,9 @@ def parse():
     p.add_argument("--planar", action="store_true", help="three separate moment planes instead of "
                    "the row-interleaved layout")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
+    p.add_argument("--n3", default="256,512", help="3d: grid sides (comma-separated)")
+    p.add_argument("--q3", default="19,27", help="3d: lattices (comma-separated)")
+    p.add_argument("--steps3", type=int, default=0, help="3d: timed steps (0: 200 at 256^3, 50 above)")
     p.add_argument("--cavities", type=int, default=512)
     p.add_argument("--max-steps", type=int, default=200000)
     p.add_argument("--requests", type=int, default=200)
@@ -546,15 +549,15 @@ def run_3d(args, torch):
     st = args.storage
     c = VALUE_BYTES[st]
     rows = []
-    for n in (256, 512):
+    for n in [int(v) for v in args.n3.split(",")]:
         g0 = np.random.default_rng(0).standard_normal((4, n, n, n), dtype=np.float32)
         rho = 1.0 + 1e-3 * g0[0].astype(np.float64)
         js = [rho * (0.01 * g0[k].astype(np.float64)) for k in (1, 2, 3)]
         del g0
-        for q in (19, 27):
+        for q in [int(v) for v in args.q3.split(",")]:
             g = Grid3D(n, n, n, q=q, prec=st, periodic=7)
             g.set_geometry(None, rho, *js)
-            steps = 200 if n == 256 else 50
+            steps = args.steps3 or (200 if n <= 256 else 50)
             g.step(10)
             g.sync()
             s = g.stream
@@ -581,7 +584,7 @@ def run_3d(args, torch):
             g.close()
             torch.cuda.empty_cache()
         del rho, js
-    head = [r for r in rows if r["n"] == 512 and r["q"] == 19][0]
+    head = max(rows, key=lambda r: (r["n"], r["q"] == 19))
     return {
         "metric": METRIC,
         "value": head["mlups"],
