@@ -221,18 +221,22 @@ enum {
 
 typedef struct {
   int32_t kernel; /* LBT1_KERNEL_* */
-  int32_t vec;    /* STRIP: columns per lane, 1, 2, 4 or 8 (must divide nx) */
-  int32_t rows;   /* STRIP: rows per strip, 6 or 14 (fused kernels also 22 and 30 for some
-                     precisions; lbt1_set_kernel says EINVAL for a shape that is not built) */
+  int32_t vec;    /* STRIP: columns per lane, 1, 2, 4 or 8.  Must divide nx on a grid
+                     periodic in x; otherwise the last chunk of a row may run into the
+                     row padding, which reads as SOLID like the outside of the axis */
+  int32_t rows;   /* STRIP: rows per strip, 6 or 14 (fused kernels also 22, and 30 for
+                     16-bit storage; lbt1_set_kernel says EINVAL for a shape that is not
+                     built) */
   int32_t waves;  /* STRIP: resident wavefronts per CU the launch aims at (1..32);
                      0 = one wavefront per strip, no grid-stride loop */
   int32_t fuse;   /* STRIP: time steps per launch.  0 or 1: one.  2 or 3: that many
                      steps in one pass over memory (the state is read and written
                      once per pass, results bit for bit those of single steps); only
                      for grids periodic in x and y without SOLID or FIXED nodes, and
-                     fuse <= vec (3: vec 4, FP32 and F16S).  Step counts that are not
-                     a multiple of fuse end with single-step launches of the same
-                     shape. */
+                     fuse <= vec (3: vec 4, FP32).  Step counts that are not a
+                     multiple of fuse end with two-step launches of the same strip
+                     shape (after three-step ones), else single-step launches of the
+                     same height, else the gather kernel. */
 } lbt1_kernel_config;
 
 /* Select the step kernel for a grid.  EINVAL if the combination is not built
