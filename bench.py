@@ -19,7 +19,8 @@ The JSON line carries:
   variants     the same run with FP64, FP16 and BF16 shifted storage, each with its
                error against the FP64 run
 
-Other workloads: --workload cavities (batched uneven cavities vs one grid per
+Other workloads: --workload cavity (the 256^2 lid-driven cavity, 50,000 steps in
+FP64 and FP32, cache-resident), --workload cavities (batched uneven cavities vs one grid per
 launch), --workload serve (continuous-batching server vs FIFO), --workload
 compare (LBMTau1 against the stored-population BGK method on the same field:
 the paper's memory comparison measured, and the speed ratio), --workload
@@ -57,7 +58,7 @@ def parse():
     p.add_argument("--steps", type=int, default=1000)
     p.add_argument("--warmup", type=int, default=100)
     p.add_argument("--workload", default="periodic",
-                   choices=["periodic", "cavities", "serve", "compare", "stability", "drop", "3d"])
+                   choices=["periodic", "cavity", "cavities", "serve", "compare", "stability", "drop", "3d"])
     p.add_argument("--n", type=int, default=8192, help="grid side of the periodic workload")
     p.add_argument("--storage", default="f32", choices=["f64", "f32", "f16s", "bf16s"])
     p.add_argument("--no-variants", action="store_true", help="skip the other storage variants")
@@ -70,6 +71,7 @@ def parse():
     p.add_argument("--n3", default="256,512", help="3d: grid sides (comma-separated)")
     p.add_argument("--q3", default="19,27", help="3d: lattices (comma-separated)")
     p.add_argument("--steps3", type=int, default=0, help="3d: timed steps (0: 200 at 256^3, 50 above)")
+    p.add_argument("--cavity-steps", type=int, default=50000, help="cavity: steps of the 256^2 cavity")
     p.add_argument("--cavities", type=int, default=512)
     p.add_argument("--max-steps", type=int, default=200000)
     p.add_argument("--requests", type=int, default=200)
@@ -357,6 +359,69 @@ def run_periodic(args, torch):
     return line
 
 
+def run_cavity(args, torch):
+    """The 256 x 256 lid-driven cavity (walls x = 0, x = 255, y = 0; lid row y = 255,
+    j = (0.1, 0)): 50,000 steps (--steps) in FP64 and FP32 storage with the autotuned
+    kernel and the FP64 residual / mass reduction every 100 steps, as in section 3's
+    convergence runs.  The grid (0.8-1.6 MB) stays in cache, so MLUPS here is no HBM
+    claim.  Beside it, the FP64 oracle runs the same cavity on the host cores."""
+    from paper_1912_09327_amd import inputs as I
+    from paper_1912_09327_amd.grid import Grid
+    n = 256
+    flags, rho, jx, jy, per = I.cavity(n, 0.1)
+    fluid = int((flags == I.FLUID).sum())
+    steps = args.cavity_steps
+    res = {}
+    for st in ("f64", "f32"):
+        g = Grid(n, n, prec=st, periodic=per)
+        g.set_geometry(flags, rho, jx, jy)
+        if not args.no_tune:
+            g.autotune(steps=30, reps=3)
+        cfg, kname = g.kernel()
+        g.step(200)
+        g.reduce()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        done = 0
+        while done < steps:
+            k = min(100, steps - done)
+            g.step(k)
+            done += k
+            d = g.reduce()                   # synchronises
+        wall = time.perf_counter() - t0
+        res[st] = dict(kernel=kname, mlups=round(fluid * steps / wall / 1e6, 1), steps_per_s=round(steps / wall, 1),
+                       us_per_step=round(wall / steps * 1e6, 2), final_residual=d["residual"],
+                       mass_drift=d["mass"] - float(rho[flags == I.FLUID].sum()))
+        log(f"[cavity] {st}: {kname}, {res[st]['mlups']:.0f} MLUPS, {res[st]['us_per_step']:.2f} us/step "
+            f"(reduction every 100 steps), residual {d['residual']:.3e}")
+        g.close()
+    line = {
+        "metric": METRIC, "value": res["f32"]["mlups"], "unit": "MLUPS", "n_gpus": 1, "steps": steps,
+        "warmup": 200, "ms_per_step": round(res["f32"]["us_per_step"] / 1e3, 6), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"256x256 lid-driven cavity, lid j = (0.1, 0), {steps} steps, FP64 and FP32 "
+                               "storage, reduction every 100 steps (cache-resident, no HBM claim)",
+                   "fluid_nodes": fluid},
+        "runs": res,
+    }
+    if not args.no_cpu:
+        import oracle
+        threads = len(os.sched_getaffinity(0))
+        oracle.set_threads(threads)
+        oracle.run(rho, jx, jy, 10, flags, per)
+        t0 = time.perf_counter()
+        oracle.run(rho, jx, jy, 1000, flags, per)
+        one = (time.perf_counter() - t0) / 1000
+        m = max(100, min(steps, int(args.cpu_seconds / max(one, 1e-6))))
+        t0 = time.perf_counter()
+        oracle.run(rho, jx, jy, m, flags, per)
+        dt = time.perf_counter() - t0
+        line["cpu_baseline"] = dict(value=round(fluid * m / dt / 1e6, 2), unit="MLUPS", cores=threads, kind="oracle",
+                                    sample=f"the same 256x256 cavity, {m} steps, FP64, {threads} OpenMP threads, "
+                                           f"{dt:.1f} s")
+    return line
+
+
 def run_compare(args, torch):
     """LBMTau1 (two fused steps per launch, and one step per launch) against the
     stored-population BGK method (tau = 1 and tau = 0.6) on the periodic field:
@@ -626,6 +691,8 @@ def main():
         line = run_drop(args, torch)
     elif args.workload == "stability":
         line = run_stability(args, torch)
+    elif args.workload == "cavity":
+        line = run_cavity(args, torch)
     elif args.workload == "compare":
         line = run_compare(args, torch)
     elif args.workload == "cavities":
