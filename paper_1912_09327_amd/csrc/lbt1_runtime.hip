@@ -321,6 +321,12 @@ lbt1_kernel_config heuristic_config(int prec, bool haswall, int wall, int nx, in
   }
   const long tall = (long)((chunks_of(nx, c.vec) + 61) / 62) * ((ny + 13) / 14);
   c.rows = tall < 8L * cus ? 6 : 14;
+  // A grid of up to 512 x 512 nodes is bound by the latency of a strip's walk
+  // down its rows, not by bandwidth: one column per lane gives the most wavefronts
+  // for the same short walk (measured on cavities of side 128 to 512: 1 column per
+  // lane and 6 rows fastest, or within 5 % of the gather kernel).
+  if ((long)nx * ny <= 512L * 512 && c.rows == 6 && find_kernel(prec, haswall, wall, KIND_STRIP, 1, 6, 1, false))
+    c.vec = 1;
   return c;
 }
 
