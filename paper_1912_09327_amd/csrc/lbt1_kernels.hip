@@ -3,6 +3,7 @@
 #include "lbt1_internal.hpp"
 #include "lbt1_bgk.hpp"
 #include "lbt1_fused.hpp"
+#include "lbt1_fused_wall.hpp"
 #include "lbt1_multiphase.hpp"
 #include "lbt1_step.hpp"
 
@@ -49,6 +50,12 @@ __global__ void __launch_bounds__(64) k_reduce_final(const double *partials, int
   {P, false, 0, KIND_STRIP, V, R, (const void *)&k_step_fused<P, V, R, K>, \
    "k_step_fused<" #P "," #V "," #R "," #K ">", K, 0}
 #define FUSED_ROWS(P, V, K) FUSED(P, V, 6, K), FUSED(P, V, 14, K)
+// two steps per launch on grids with walls, fixed nodes or non-periodic axes
+#define FUSED_WALL(P, W, V, R)                                                              \
+  {P, true, W, KIND_STRIP, V, R, (const void *)&k_step_fused_wall<P, W, V, R>,           \
+   "k_step_fused_wall<" #P "," #W "," #V "," #R ">", 2, 0}
+#define FUSED_WALL_ALL(P) \
+  FUSED_WALL(P, 0, 2, 6), FUSED_WALL(P, 0, 2, 14), FUSED_WALL(P, 1, 2, 6), FUSED_WALL(P, 1, 2, 14)
 #define FUSED_TALL(P, V, K) FUSED(P, V, 22, K), FUSED(P, V, 30, K)
 #define STRIP_WALLS(P, V, R) STRIP(P, false, 0, V, R), STRIP(P, true, 0, V, R), STRIP(P, true, 1, V, R)
 #define STRIP_ROWS(P, V) STRIP_WALLS(P, V, 6), STRIP_WALLS(P, V, 14)
@@ -86,6 +93,7 @@ static const StepKernel kTable[] = {
     FUSED_ROWS(P_F64, 2, 2),   FUSED_ROWS(P_F32, 2, 2),   FUSED_ROWS(P_F32, 4, 2),
     FUSED_ROWS(P_F16S, 2, 2),  FUSED_ROWS(P_F16S, 4, 2),  FUSED_ROWS(P_BF16S, 2, 2),
     FUSED_ROWS(P_BF16S, 4, 2),
+    FUSED_WALL_ALL(P_F64), FUSED_WALL_ALL(P_F32), FUSED_WALL_ALL(P_F16S), FUSED_WALL_ALL(P_BF16S),
     BGK_ALL(P_F64), BGK_ALL(P_F32), BGK_ALL(P_F16S), BGK_ALL(P_BF16S),
     SC_ALL(P_F64, 2),  SC_ALL(P_F32, 2),  SC_STRIP(P_F32, 4, 6), SC_STRIP(P_F32, 4, 14),
     SC_ALL(P_F16S, 2), SC_ALL(P_BF16S, 2),

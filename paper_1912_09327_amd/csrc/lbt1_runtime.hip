@@ -312,6 +312,21 @@ lbt1_kernel_config heuristic_config(int prec, bool haswall, int wall, int nx, in
       }
     }
   }
+  if (haswall && strip_fits(nx, 2, px) && 62 * 2 <= std::max(62, nx)) {
+    // two fused steps at 2 columns per lane on grids with walls (measured on
+    // cavities of side 256, 1024 and 4096: fastest in FP32 and 16-bit storage at
+    // every size, in FP64 at 256 and 4096 and within 6 % at 1024); 14-row strips
+    // where there are enough of them, else 6 (a short walk for small grids)
+    const long sx = (chunks_of(nx, 2) + 61) / 62;
+    const int r = sx * ((ny + 13) / 14) >= 8L * cus ? 14 : 6;
+    if (find_kernel(prec, true, wall, KIND_STRIP, 2, r, 2, false)) {
+      c.vec = 2;
+      c.rows = r;
+      c.fuse = 2;
+      c.waves = 0;
+      return c;
+    }
+  }
   const int cands[] = {8, 4, 2, 1};
   for (int v : cands) {
     if (strip_fits(nx, v, px) && 62 * v <= std::max(62, nx) && find_kernel(prec, haswall, wall, KIND_STRIP, v, 14, 1, false)) {
@@ -367,8 +382,8 @@ lbt1_status bind_config(lbt1_grid *g, const lbt1_kernel_config &want, int cus) {
     if (c.waves < 0 || c.waves > 32) return fail(LBT1_EINVAL, "waves %d out of range", c.waves);
     if (c.fuse == 0) c.fuse = 1;
     if (c.fuse < 1 || c.fuse > c.vec) return fail(LBT1_EINVAL, "fuse %d must be between 1 and vec %d", c.fuse, c.vec);
-    if (c.fuse > 1 && g->haswall)
-      return fail(LBT1_EINVAL, "fused steps need a grid periodic in x and y without SOLID or FIXED nodes");
+    if (c.fuse > 2 && g->haswall)
+      return fail(LBT1_EINVAL, "three fused steps need a grid periodic in x and y without SOLID or FIXED nodes");
     if (c.fuse > 1 && g->mp) return fail(LBT1_EINVAL, "multiphase grids take one step per launch");
     if (g->mp && g->haswall)
       return fail(LBT1_EINVAL, "multiphase strips need a grid periodic in x and y without SOLID nodes (use gather)");
@@ -1184,7 +1199,7 @@ lbt1_status lbt1_autotune(lbt1_grid *g, int32_t steps, int32_t reps, lbt1_kernel
       for (int w : waves)
         for (int f : fuses) {
           if (!strip_fits(g->nx, v, g->periodic & 1u)) continue;
-          if (f > 1 && (g->haswall || g->mp)) continue;
+          if ((f > 1 && g->mp) || (f > 2 && g->haswall)) continue;
           if (g->mp && g->haswall) continue;
           if (!find_kernel(g->prec, g->haswall, g->wall, KIND_STRIP, v, r, f, g->mp)) continue;
           if (64 * v > 2 * std::max(64, g->nx)) continue;

@@ -94,8 +94,8 @@ def test_fused_refused_where_it_does_not_apply():
     g = Grid(64, 32, prec="f32", periodic=per)
     try:
         g.set_geometry(flags)
-        with pytest.raises(C.Lbt1Error) as e:            # walls
-            g.set_kernel("strip", vec=2, rows=6, fuse=2)
+        with pytest.raises(C.Lbt1Error) as e:            # three steps need a grid without walls
+            g.set_kernel("strip", vec=4, rows=14, fuse=3)
         assert e.value.status == C.EINVAL
     finally:
         g.close()
