@@ -231,9 +231,10 @@ typedef struct {
                      0 = one wavefront per strip, no grid-stride loop */
   int32_t fuse;   /* STRIP: time steps per launch.  0 or 1: one.  2 or 3: that many
                      steps in one pass over memory (the state is read and written
-                     once per pass, results bit for bit those of single steps); only
-                     for grids periodic in x and y without SOLID or FIXED nodes, and
-                     fuse <= vec (3: vec 4, FP32).  Step counts that are not a
+                     once per pass, results bit for bit those of single steps);
+                     fuse <= vec.  3: vec 4, FP32, grids periodic in x and y without
+                     SOLID or FIXED nodes.  2: any grid that is not multiphase (with
+                     walls, fixed nodes or open axes: vec 2, rows 6 or 14).  Step counts that are not a
                      multiple of fuse end with two-step launches of the same strip
                      shape (after three-step ones), else single-step launches of the
                      same height, else the gather kernel. */
