@@ -85,7 +85,9 @@ __device__ __forceinline__ void fused_feed(FusedStage<P, VEC> &st, const bool em
   }
 }
 
-template <int P, int VEC, int NY, int K>
+// UNIT: both storage scales are 1 (the default), so the codec's scaling
+// multiplications are exact no-ops and are left out.
+template <int P, int VEC, int NY, int K, bool UNIT>
 __device__ __forceinline__ void fused_body(const StepArgs &a, const int chunk0, const int y0, const int lane) {
   using T = Traits<P>;
   using C = typename T::C;
@@ -132,7 +134,7 @@ __device__ __forceinline__ void fused_body(const StepArgs &a, const int chunk0, 
       d[v] = T::dec(raw[0].v[v]);
       jx[v] = T::dec(raw[1].v[v]);
       jy[v] = T::dec(raw[2].v[v]);
-      if (T::kScaled) {
+      if (T::kScaled && !UNIT) {
         d[v] *= sd;
         jx[v] *= sj;
         jy[v] *= sj;
@@ -143,7 +145,7 @@ __device__ __forceinline__ void fused_body(const StepArgs &a, const int chunk0, 
 #pragma unroll
     for (int v = 0; v < VEC; ++v) {
       C x0 = d[v], x1 = jx[v], x2 = jy[v];
-      if (T::kScaled) {
+      if (T::kScaled && !UNIT) {
         x0 *= ed;
         x1 *= ej;
         x2 *= ej;
@@ -217,7 +219,17 @@ k_step_fused(StepArgs a, StripMap m) {
     const int s = u * 4 + wave;  // same strip order as the single-step kernel
     const int sy = s / m.strips_x;
     const int sx = s - sy * m.strips_x;
-    if (sy < m.strips_y) fused_body<P, VEC, NY, K>(a, sx * 62, sy * NY, lane);
+    if (sy >= m.strips_y) continue;
+    if constexpr (Traits<P>::kScaled) {
+      // 16-bit storage is bound by vector-ALU issue: with unit scales (wave-uniform
+      // test) the body without the scaling multiplications runs
+      if (a.sc_d == 1.0 && a.sc_j == 1.0 && a.is_d == 1.0 && a.is_j == 1.0)
+        fused_body<P, VEC, NY, K, true>(a, sx * 62, sy * NY, lane);
+      else
+        fused_body<P, VEC, NY, K, false>(a, sx * 62, sy * NY, lane);
+    } else {
+      fused_body<P, VEC, NY, K, true>(a, sx * 62, sy * NY, lane);
+    }
   }
 }
 

@@ -36,7 +36,7 @@ struct WallStage {
 // form raw, SOLID and FLUID bits per column.  When emit_row, the pending target
 // row (the row before this one) is completed into out (storage form) with its
 // SOLID and FLUID bits.
-template <int P, int WALL, int VEC>
+template <int P, int WALL, int VEC, bool UNIT>
 __device__ __forceinline__ void wall_feed(WallStage<P, WALL, VEC> &st, const bool odd, const bool emit_row,
                                           const typename Traits<P>::C (&d)[VEC],
                                           const typename Traits<P>::C (&jx)[VEC],
@@ -98,7 +98,7 @@ __device__ __forceinline__ void wall_feed(WallStage<P, WALL, VEC> &st, const boo
       C dn, jxn, jyn;
       finish<C>(row_sum(g5, g2, g6), row_dif(g5, g6), row_sum(g1, g0, g3), row_dif(g1, g3), row_sum(g8, g4, g7),
                 row_dif(g8, g7), dn, jxn, jyn);
-      if (T::kScaled) {
+      if (T::kScaled && !UNIT) {
         dn *= ed;
         jxn *= ej;
         jyn *= ej;
@@ -147,7 +147,9 @@ __device__ __forceinline__ void wall_feed(WallStage<P, WALL, VEC> &st, const boo
   st.own_raw[2] = raw[2];
 }
 
-template <int P, int WALL, int VEC, int NY>
+// UNIT: both storage scales are 1 (the default), so the codec's scaling
+// multiplications are exact no-ops and are left out.
+template <int P, int WALL, int VEC, int NY, bool UNIT>
 __device__ __forceinline__ void fused_wall_body(const StepArgs &a, const int chunk0, const int y0, const int lane) {
   using T = Traits<P>;
   using C = typename T::C;
@@ -205,7 +207,7 @@ __device__ __forceinline__ void fused_wall_body(const StepArgs &a, const int chu
       d[v] = T::dec(raw[0].v[v]);
       jx[v] = T::dec(raw[1].v[v]);
       jy[v] = T::dec(raw[2].v[v]);
-      if (T::kScaled) {
+      if (T::kScaled && !UNIT) {
         d[v] *= sd;
         jx[v] *= sj;
         jy[v] *= sj;
@@ -234,7 +236,7 @@ __device__ __forceinline__ void fused_wall_body(const StepArgs &a, const int chu
     decode(cur.raw, d, jx, jy);
     SP mid[3];
     uint32_t ms = 0, mf = 0;
-    wall_feed<P, WALL, VEC>(stage[0], (i & 1) != 0, i >= 2, d, jx, jy, cur.raw, sbits, fbits, Fx, Fy, ed, ej, mid,
+    wall_feed<P, WALL, VEC, UNIT>(stage[0], (i & 1) != 0, i >= 2, d, jx, jy, cur.raw, sbits, fbits, Fx, Fy, ed, ej, mid,
                             ms, mf);
     if (i < 2) continue;
     // stage 1 receives row j = i - 2 (lattice row y0 - 1 + j), a row of step t+1
@@ -242,7 +244,7 @@ __device__ __forceinline__ void fused_wall_body(const StepArgs &a, const int chu
     decode(mid, d, jx, jy);
     SP out[3];
     uint32_t os = 0, of = 0;
-    wall_feed<P, WALL, VEC>(stage[1], (j & 1) != 0, j >= 2, d, jx, jy, mid, ms, mf, Fx, Fy, ed, ej, out, os, of);
+    wall_feed<P, WALL, VEC, UNIT>(stage[1], (j & 1) != 0, j >= 2, d, jx, jy, mid, ms, mf, Fx, Fy, ed, ej, out, os, of);
     if (j < 2) continue;
     // rows past ny and lanes past nx write to the trash area (no branch)
     const int t = y0 + j - 2;  // lattice row of step t+2 leaving stage 1
@@ -269,7 +271,15 @@ __global__ void __launch_bounds__(256) k_step_fused_wall(StepArgs a, StripMap m)
     const int s = u * 4 + wave;  // same strip order as the single-step kernel
     const int sy = s / m.strips_x;
     const int sx = s - sy * m.strips_x;
-    if (sy < m.strips_y) fused_wall_body<P, WALL, VEC, NY>(a, sx * 62, sy * NY, lane);
+    if (sy >= m.strips_y) continue;
+    if constexpr (Traits<P>::kScaled) {
+      if (a.sc_d == 1.0 && a.sc_j == 1.0 && a.is_d == 1.0 && a.is_j == 1.0)  // wave-uniform
+        fused_wall_body<P, WALL, VEC, NY, true>(a, sx * 62, sy * NY, lane);
+      else
+        fused_wall_body<P, WALL, VEC, NY, false>(a, sx * 62, sy * NY, lane);
+    } else {
+      fused_wall_body<P, WALL, VEC, NY, true>(a, sx * 62, sy * NY, lane);
+    }
   }
 }
 

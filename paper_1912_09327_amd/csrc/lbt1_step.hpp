@@ -105,7 +105,9 @@ constexpr int kPrefetch = 2;
 // next door through one shuffle and no separate halo pass is needed.  The halo
 // chunks are aligned vector loads of cache lines the neighbouring strips read
 // at the same time.
-template <int P, bool HASWALL, int WALL, int VEC, int NY>
+// UNIT: both storage scales are 1 (the default), so the codec's scaling
+// multiplications are exact no-ops and are left out.
+template <int P, bool HASWALL, int WALL, int VEC, int NY, bool UNIT = false>
 __device__ __forceinline__ void strip_body(const StepArgs &a, const int chunk0, const int y0,
                                            const int lane) {
   using T = Traits<P>;
@@ -189,7 +191,7 @@ __device__ __forceinline__ void strip_body(const StepArgs &a, const int chunk0, 
 #pragma unroll
     for (int v = 0; v < VEC; ++v) {
       C d = T::dec(raw[0].v[v]), jx = T::dec(raw[1].v[v]), jy = T::dec(raw[2].v[v]);
-      if (T::kScaled) {
+      if (T::kScaled && !UNIT) {
         d *= sd;
         jx *= sj;
         jy *= sj;
@@ -261,7 +263,7 @@ __device__ __forceinline__ void strip_body(const StepArgs &a, const int chunk0, 
           finish<C>(up_old.s[v], up_old.x[v], lev.s[v], lev.x[v], row_sum(a8, a4, a7),
                     row_dif(a8, a7), dn, jxn, jyn);
         }
-        if (T::kScaled) {
+        if (T::kScaled && !UNIT) {
           dn *= ed;
           jxn *= ej;
           jyn *= ej;
@@ -477,10 +479,20 @@ __global__ void __launch_bounds__(256) k_step_batch(BatchStepArgs b) {
     a.trash = g.trash;
     const int sy = item.y / g.strips_x;   // along each row band, as in k_step_strip
     const int sx = item.y - sy * g.strips_x;
-    if (g.wall == WALL_PAPER)
-      strip_body<P, true, WALL_PAPER, VEC, NY>(a, sx * 62, sy * NY, lane);
-    else
-      strip_body<P, true, WALL_HALFWAY, VEC, NY>(a, sx * 62, sy * NY, lane);
+    // unit storage scales (the default; a wave-uniform test): the body without
+    // the scaling multiplications, which are exact no-ops then
+    const bool unit = !Traits<P>::kScaled || (g.sc_d == 1.0 && g.sc_j == 1.0 && g.is_d == 1.0 && g.is_j == 1.0);
+    if (g.wall == WALL_PAPER) {
+      if (!Traits<P>::kScaled || unit)
+        strip_body<P, true, WALL_PAPER, VEC, NY, true>(a, sx * 62, sy * NY, lane);
+      else
+        strip_body<P, true, WALL_PAPER, VEC, NY, false>(a, sx * 62, sy * NY, lane);
+    } else {
+      if (!Traits<P>::kScaled || unit)
+        strip_body<P, true, WALL_HALFWAY, VEC, NY, true>(a, sx * 62, sy * NY, lane);
+      else
+        strip_body<P, true, WALL_HALFWAY, VEC, NY, false>(a, sx * 62, sy * NY, lane);
+    }
   }
 }
 
