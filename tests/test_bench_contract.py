@@ -1,0 +1,68 @@
+"""CPU checks of bench.py's contract: more than one GPU is refused with a message,
+the roofline peaks are the stated ones, and counted traffic / instruction figures
+are used only when they were taken on the kernel that runs and its sources."""
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _bench():
+    sys.path.insert(0, ROOT)
+    import bench
+    return bench
+
+
+@pytest.mark.parametrize("n", [2, 8])
+def test_more_than_one_gpu_is_refused(n):
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", str(n)],
+                       capture_output=True, text=True, timeout=120, cwd=ROOT)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""              # no JSON line
+
+
+def test_roofline_peaks():
+    b = _bench()
+    assert b.HBM_PEAK_GBPS == 8000.0
+    # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+    assert b.VALU_PEAK_TOPS == pytest.approx(39.3216)
+    assert b.ALG_OPS_PER_LUP["f32"] == 32 + 14
+    assert b.ALG_OPS_PER_LUP["f16s"] > b.ALG_OPS_PER_LUP["f32"]
+
+
+def test_counted_figures_need_matching_kernel_and_sources(tmp_path, monkeypatch):
+    b = _bench()
+    h = b.kernel_source_hash()
+    assert len(h) == 16
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    rec = {"f32": {"source_hash": h, "kernel_bench": "k_step_fused<P_F32,4,22,3>", "traffic_bytes": 2.0e9,
+                   "traffic_ratio": 1.25, "valu_per_dispatch": 1.0e8}}
+    (prof / "traffic_periodic8192.json").write_text(json.dumps(rec))
+    (prof / "valu_periodic8192.json").write_text(json.dumps(rec))
+    monkeypatch.setattr(b, "ROOT", str(tmp_path))
+    # kernel_source_hash reads the sources under ROOT: point it back at the repository
+    monkeypatch.setattr(b, "kernel_source_hash", lambda: h)
+    t = b.measured_traffic("f32", "k_step_fused<P_F32,4,22,3>", 0.5)
+    assert t["GBps"] == pytest.approx(2.0e9 / 0.5e-3 / 1e9) and t["ratio"] == 1.25
+    assert b.measured_valu("f32", "k_step_fused<P_F32,4,22,3>") == 64 * 1.0e8
+    # another kernel, another storage format or other sources: no figure
+    assert b.measured_traffic("f32", "k_step_fused<P_F32,4,14,3>", 0.5) is None
+    assert b.measured_traffic("f16s", "k_step_fused<P_F32,4,22,3>", 0.5) is None
+    monkeypatch.setattr(b, "kernel_source_hash", lambda: "0" * 16)
+    assert b.measured_traffic("f32", "k_step_fused<P_F32,4,22,3>", 0.5) is None
+    assert b.measured_valu("f32", "k_step_fused<P_F32,4,22,3>") is None
+
+
+def test_committed_profiles_match_the_sources():
+    """The committed counter summaries were taken on the current kernel sources."""
+    b = _bench()
+    for name in ("traffic_periodic8192.json", "valu_periodic8192.json"):
+        rec = json.load(open(os.path.join(ROOT, "profiles", name)))
+        for st, r in rec.items():
+            assert r["source_hash"] == b.kernel_source_hash(), (name, st)
