@@ -111,3 +111,25 @@ def test_fused_wall_refusals():
         g.step(3)
     finally:
         g.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16s"])
+@pytest.mark.parametrize("shape", [(130, 3), (131, 4), (64, 5), (6, 9)])
+@pytest.mark.parametrize("kind", ["open", "channel", "obstacles_walls"])
+def test_fused_wall_thin_grids(prec, shape, kind):
+    """Grids of 3 to 9 rows or 6 columns: every strip row is a halo or wrapped row."""
+    nx, ny = shape
+    if kind == "channel" and nx % 2:
+        pytest.skip("periodic in x: 2 columns per lane need an even width")
+    if kind == "channel":
+        flags, per = I.channel(nx, ny)
+        rho, jx, jy = I.random_state(nx, ny, np.random.default_rng(nx + ny))
+    else:
+        flags, rho, jx, jy, per = _case(kind, nx, ny, nx + 3 * ny)
+    F = (1e-5, 3e-6)
+    base = gpu_run(flags, rho, jx, jy, 13, prec, "halfway", per, F, kernel=GATHER)
+    for rows in (6, 14):
+        got = gpu_run(flags, rho, jx, jy, 13, prec, "halfway", per, F,
+                      kernel=dict(kernel="strip", vec=2, rows=rows, waves=0, fuse=2))
+        for a, b in zip(base, got):
+            assert np.array_equal(a, b), rows
