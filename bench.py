@@ -71,7 +71,8 @@ def parse():
     p.add_argument("--n3", default="256,512", help="3d: grid sides (comma-separated)")
     p.add_argument("--q3", default="19,27", help="3d: lattices (comma-separated)")
     p.add_argument("--steps3", type=int, default=0, help="3d: timed steps (0: 200 at 256^3, 50 above)")
-    p.add_argument("--cavity-steps", type=int, default=50000, help="cavity: steps of the 256^2 cavity")
+    p.add_argument("--cavity-steps", type=int, default=50000, help="cavity: steps of the lid-driven cavity")
+    p.add_argument("--cavity-n", type=int, default=256, help="cavity: side of the lid-driven cavity")
     p.add_argument("--cavities", type=int, default=512)
     p.add_argument("--max-steps", type=int, default=200000)
     p.add_argument("--requests", type=int, default=200)
@@ -369,7 +370,7 @@ def run_cavity(args, torch):
     claim.  Beside it, the FP64 oracle runs the same cavity on the host cores."""
     from paper_1912_09327_amd import inputs as I
     from paper_1912_09327_amd.grid import Grid
-    n = 256
+    n = args.cavity_n
     flags, rho, jx, jy, per = I.cavity(n, 0.1)
     fluid = int((flags == I.FLUID).sum())
     steps = args.cavity_steps
@@ -401,8 +402,8 @@ def run_cavity(args, torch):
         "metric": METRIC, "value": res["f32"]["mlups"], "unit": "MLUPS", "n_gpus": 1, "steps": steps,
         "warmup": 200, "ms_per_step": round(res["f32"]["us_per_step"] / 1e3, 6), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"256x256 lid-driven cavity, lid j = (0.1, 0), {steps} steps, FP64 and FP32 "
-                               "storage, reduction every 100 steps (cache-resident, no HBM claim)",
+        "config": {"workload": f"{n}x{n} lid-driven cavity, lid j = (0.1, 0), {steps} steps, FP64 and FP32 "
+                               "storage, reduction every 100 steps" + (" (cache-resident, no HBM claim)" if n <= 1024 else ""),
                    "fluid_nodes": fluid},
         "runs": res,
     }
@@ -410,16 +411,17 @@ def run_cavity(args, torch):
         import oracle
         threads = len(os.sched_getaffinity(0))
         oracle.set_threads(threads)
-        oracle.run(rho, jx, jy, 10, flags, per)
+        probe = max(1, min(1000, int(2e8 / (n * n))))      # about 0.5 s of oracle work
+        oracle.run(rho, jx, jy, 1, flags, per)
         t0 = time.perf_counter()
-        oracle.run(rho, jx, jy, 1000, flags, per)
-        one = (time.perf_counter() - t0) / 1000
-        m = max(100, min(steps, int(args.cpu_seconds / max(one, 1e-6))))
+        oracle.run(rho, jx, jy, probe, flags, per)
+        one = (time.perf_counter() - t0) / probe
+        m = max(1, min(steps, int(args.cpu_seconds / max(one, 1e-6))))
         t0 = time.perf_counter()
         oracle.run(rho, jx, jy, m, flags, per)
         dt = time.perf_counter() - t0
         line["cpu_baseline"] = dict(value=round(fluid * m / dt / 1e6, 2), unit="MLUPS", cores=threads, kind="oracle",
-                                    sample=f"the same 256x256 cavity, {m} steps, FP64, {threads} OpenMP threads, "
+                                    sample=f"the same {n}x{n} cavity, {m} steps, FP64, {threads} OpenMP threads, "
                                            f"{dt:.1f} s")
     return line
 
