@@ -74,6 +74,10 @@ __global__ void __launch_bounds__(64) k_reduce_final(const double *partials, int
   {P, HW, W, KIND_GATHER, 0, 0, (const void *)&k_step_sc_gather<P, HW, W>, "k_step_sc_gather<" #P "," #HW "," #W ">", 1, 1}
 #define SC_STRIP(P, V, R) \
   {P, false, 0, KIND_STRIP, V, R, (const void *)&k_step_sc_strip<P, V, R>, "k_step_sc_strip<" #P "," #V "," #R ">", 1, 1}
+// two multiphase steps per launch (4 columns per lane: each step widens the
+// wrong halo columns by two)
+#define SC_FUSED(P, V, R) \
+  {P, false, 0, KIND_STRIP, V, R, (const void *)&k_step_sc_fused<P, V, R>, "k_step_sc_fused<" #P "," #V "," #R ">", 2, 1}
 #define SC_ALL(P, V)                                                                                \
   SC_GATHER(P, false, 0), SC_GATHER(P, true, 0), SC_GATHER(P, true, 1), SC_STRIP(P, V, 6), SC_STRIP(P, V, 14)
 
@@ -96,6 +100,7 @@ static const StepKernel kTable[] = {
     FUSED_WALL_ALL(P_F64), FUSED_WALL_ALL(P_F32), FUSED_WALL_ALL(P_F16S), FUSED_WALL_ALL(P_BF16S),
     BGK_ALL(P_F64), BGK_ALL(P_F32), BGK_ALL(P_F16S), BGK_ALL(P_BF16S),
     SC_ALL(P_F64, 2),  SC_ALL(P_F32, 2),  SC_STRIP(P_F32, 4, 6), SC_STRIP(P_F32, 4, 14),
+    SC_FUSED(P_F32, 4, 6), SC_FUSED(P_F32, 4, 14),
     SC_ALL(P_F16S, 2), SC_ALL(P_BF16S, 2),
 };
 

@@ -384,7 +384,7 @@ lbt1_status bind_config(lbt1_grid *g, const lbt1_kernel_config &want, int cus) {
     if (c.fuse < 1 || c.fuse > c.vec) return fail(LBT1_EINVAL, "fuse %d must be between 1 and vec %d", c.fuse, c.vec);
     if (c.fuse > 2 && g->haswall)
       return fail(LBT1_EINVAL, "three fused steps need a grid periodic in x and y without SOLID or FIXED nodes");
-    if (c.fuse > 1 && g->mp) return fail(LBT1_EINVAL, "multiphase grids take one step per launch");
+    if (c.fuse > 2 && g->mp) return fail(LBT1_EINVAL, "multiphase grids take one or two steps per launch");
     if (g->mp && g->haswall)
       return fail(LBT1_EINVAL, "multiphase strips need a grid periodic in x and y without SOLID nodes (use gather)");
     k = find_kernel(g->prec, g->haswall, g->wall, KIND_STRIP, c.vec, c.rows, c.fuse, g->mp);
@@ -1199,7 +1199,7 @@ lbt1_status lbt1_autotune(lbt1_grid *g, int32_t steps, int32_t reps, lbt1_kernel
       for (int w : waves)
         for (int f : fuses) {
           if (!strip_fits(g->nx, v, g->periodic & 1u)) continue;
-          if ((f > 1 && g->mp) || (f > 2 && g->haswall)) continue;
+          if (f > 2 && (g->mp || g->haswall)) continue;
           if (g->mp && g->haswall) continue;
           if (!find_kernel(g->prec, g->haswall, g->wall, KIND_STRIP, v, r, f, g->mp)) continue;
           if (64 * v > 2 * std::max(64, g->nx)) continue;

@@ -186,3 +186,37 @@ def test_sc_refusals():
         assert e.value.status == C.EINVAL
     finally:
         h.close()
+
+
+@pytest.mark.parametrize("shape", [(512, 77), (248, 33), (8, 5)])
+def test_sc_fused_bitwise_equals_gather(shape):
+    """Two multiphase steps per launch (4 columns per lane) give the bits of single
+    steps, for odd step counts too (a single-step strip finishes them)."""
+    nx, ny = shape
+    flags, rho, jx, jy, per = _case("periodic", nx, ny, 6)
+    base, _ = _gpu(flags, rho, jx, jy, 25, "f32", "paper", per, (1e-5, 0.0), kernel=dict(kernel="gather"))
+    for rows in (6, 14):
+        for waves in (0, 8):
+            got, name = _gpu(flags, rho, jx, jy, 25, "f32", "paper", per, (1e-5, 0.0),
+                             kernel=dict(kernel="strip", vec=4, rows=rows, waves=waves, fuse=2))
+            assert "sc_fused" in name
+            for a, b in zip(base, got):
+                assert np.array_equal(a, b), (rows, waves)
+
+
+def test_sc_fused_bursts_and_splitting():
+    from paper_1912_09327_amd.grid import Grid
+    nx, ny = 372, 90
+    flags, rho, jx, jy, per = _case("periodic", nx, ny, 7)
+    ref, _ = _gpu(flags, rho, jx, jy, 231, "f32", "paper", per, kernel=dict(kernel="gather"))
+    g = Grid(nx, ny, prec="f32", periodic=per, multiphase=SC)
+    try:
+        g.set_geometry(flags, rho, jx, jy)
+        g.set_kernel("strip", vec=4, rows=14, waves=0, fuse=2)
+        for n in (1, 64, 3, 128, 21, 2, 4, 5, 1, 2):
+            g.step(n)
+        got = g.read_moments()
+    finally:
+        g.close()
+    for a, b in zip(ref, got):
+        assert np.array_equal(a, b)
