@@ -54,8 +54,10 @@ __global__ void __launch_bounds__(64) k_reduce_final(const double *partials, int
 #define FUSED_WALL(P, W, V, R)                                                              \
   {P, true, W, KIND_STRIP, V, R, (const void *)&k_step_fused_wall<P, W, V, R>,           \
    "k_step_fused_wall<" #P "," #W "," #V "," #R ">", 2, 0}
-#define FUSED_WALL_ALL(P) \
-  FUSED_WALL(P, 0, 2, 6), FUSED_WALL(P, 0, 2, 14), FUSED_WALL(P, 1, 2, 6), FUSED_WALL(P, 1, 2, 14)
+// (2-row strips: the shortest walk, for small grids bound by its latency)
+#define FUSED_WALL_ALL(P)                                                                       \
+  FUSED_WALL(P, 0, 2, 2), FUSED_WALL(P, 0, 2, 6), FUSED_WALL(P, 0, 2, 14), FUSED_WALL(P, 1, 2, 2), \
+      FUSED_WALL(P, 1, 2, 6), FUSED_WALL(P, 1, 2, 14)
 #define FUSED_TALL(P, V, K) FUSED(P, V, 22, K), FUSED(P, V, 30, K)
 #define STRIP_WALLS(P, V, R) STRIP(P, false, 0, V, R), STRIP(P, true, 0, V, R), STRIP(P, true, 1, V, R)
 #define STRIP_ROWS(P, V) STRIP_WALLS(P, V, 6), STRIP_WALLS(P, V, 14)

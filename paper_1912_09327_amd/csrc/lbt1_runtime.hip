@@ -315,10 +315,12 @@ lbt1_kernel_config heuristic_config(int prec, bool haswall, int wall, int nx, in
   if (haswall && strip_fits(nx, 2, px) && 62 * 2 <= std::max(62, nx)) {
     // two fused steps at 2 columns per lane on grids with walls (measured on
     // cavities of side 256, 1024 and 4096: fastest in FP32 and 16-bit storage at
-    // every size, in FP64 at 256 and 4096 and within 6 % at 1024); 14-row strips
-    // where there are enough of them, else 6 (a short walk for small grids)
+    // every size, in FP64 at 256 and 4096 and within 6 % at 1024).  Strip height:
+    // up to 512 x 512 nodes 2 rows (the step is bound by the latency of a strip's
+    // walk: 2.9 us against 5.0 at 6 rows on a 256^2 cavity), else 14 where there
+    // are enough strips, else 6
     const long sx = (chunks_of(nx, 2) + 61) / 62;
-    const int r = sx * ((ny + 13) / 14) >= 8L * cus ? 14 : 6;
+    const int r = (long)nx * ny <= 512L * 512 ? 2 : sx * ((ny + 13) / 14) >= 8L * cus ? 14 : 6;
     if (find_kernel(prec, true, wall, KIND_STRIP, 2, r, 2, false)) {
       c.vec = 2;
       c.rows = r;
@@ -1191,7 +1193,7 @@ lbt1_status lbt1_autotune(lbt1_grid *g, int32_t steps, int32_t reps, lbt1_kernel
     cands.push_back(c);
   }
   const int vecs[] = {1, 2, 4, 8};
-  const int rows[] = {6, 14, 22, 30};
+  const int rows[] = {2, 6, 14, 22, 30};
   const int waves[] = {0, 8, 16};
   const int fuses[] = {1, 2, 3};
   for (int v : vecs)
