@@ -154,17 +154,26 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
+def profile_record(name, storage, kernel_name):
+    """The record of `kernel_name` for `storage` in a committed counter summary
+    (one record, or a list of them for several strip shapes), if it was taken on
+    these kernel sources; None otherwise."""
+    try:
+        recs = json.load(open(os.path.join(ROOT, "profiles", name)))[storage]
+    except (OSError, KeyError, ValueError):
+        return None
+    for rec in recs if isinstance(recs, list) else [recs]:
+        if rec.get("source_hash") == kernel_source_hash() and rec.get("kernel_bench") == kernel_name:
+            return rec
+    return None
+
+
 def measured_valu(storage, kernel_name):
     """Vector-ALU lane operations per launch of the step kernel from the committed
     rocprofv3 summary (profiles/valu_periodic8192.json: SQ_INSTS_VALU per dispatch
     times 64 lanes), if it was taken on this kernel and these kernel sources."""
-    try:
-        rec = json.load(open(os.path.join(ROOT, "profiles", "valu_periodic8192.json")))[storage]
-    except (OSError, KeyError, ValueError):
-        return None
-    if rec.get("source_hash") != kernel_source_hash() or rec.get("kernel_bench") != kernel_name:
-        return None
-    return rec["valu_per_dispatch"] * 64
+    rec = profile_record("valu_periodic8192.json", storage, kernel_name)
+    return None if rec is None else rec["valu_per_dispatch"] * 64
 
 
 def measured_traffic(storage, kernel_name, kernel_ms):
@@ -172,12 +181,8 @@ def measured_traffic(storage, kernel_name, kernel_ms):
     (profiles/traffic_periodic8192.json: FETCH_SIZE and WRITE_SIZE per dispatch, each
     scaled by what the counter reads for a copy of known size), if it was taken on this
     kernel and these kernel sources; None otherwise."""
-    path = os.path.join(ROOT, "profiles", "traffic_periodic8192.json")
-    try:
-        rec = json.load(open(path))[storage]
-    except (OSError, KeyError, ValueError):
-        return None
-    if rec.get("source_hash") != kernel_source_hash() or rec.get("kernel_bench") != kernel_name:
+    rec = profile_record("traffic_periodic8192.json", storage, kernel_name)
+    if rec is None:
         return None
     return dict(bytes_per_launch=rec["traffic_bytes"], ratio=rec["traffic_ratio"],
                 GBps=rec["traffic_bytes"] / (kernel_ms * 1e-3) / 1e9)

@@ -224,8 +224,8 @@ typedef struct {
   int32_t vec;    /* STRIP: columns per lane, 1, 2, 4 or 8.  Must divide nx on a grid
                      periodic in x; otherwise the last chunk of a row may run into the
                      row padding, which reads as SOLID like the outside of the axis */
-  int32_t rows;   /* STRIP: rows per strip, 6 or 14 (fused kernels also 22, and 30 for
-                     16-bit storage; two steps on grids with walls also 2; lbt1_set_kernel
+  int32_t rows;   /* STRIP: rows per strip, 6 or 14 (fused kernels also 22; 28 for three
+                     FP32 steps, 30 for 16-bit storage; two steps on grids with walls also 2; lbt1_set_kernel
                      says EINVAL for a shape that is not built) */
   int32_t waves;  /* STRIP: resident wavefronts per CU the launch aims at (1..32);
                      0 = one wavefront per strip, no grid-stride loop */
@@ -248,11 +248,15 @@ lbt1_status lbt1_set_kernel(lbt1_grid *g, const lbt1_kernel_config *cfg);
  * symbol-like name, NUL-terminated, at most name_cap bytes. */
 lbt1_status lbt1_get_kernel(lbt1_grid *g, lbt1_kernel_config *cfg, char *name, size_t name_cap);
 
-/* Time every built configuration that fits this grid on a scratch copy of it
- * (`steps` steps each, best of `reps`), select the fastest and return it in
- * *best (optional) and its time per step in *ms_per_step (optional).  The
- * grid's state is unchanged.  The result is remembered for grids of the same
- * precision, flag use and size in this process. */
+/* Time every built configuration that fits this grid, on the grid's own memory
+ * (its state is saved to scratch memory first and restored afterwards):
+ * `steps` steps each, best of `reps`; then those within 5 % of the fastest (at
+ * most eight) again as lbt1_step runs them, in graph bursts of 64 steps (three
+ * bursts each, in interleaved rounds, best of max(reps, 3)).  Selects the
+ * fastest and returns it in *best (optional) and its time per step in
+ * *ms_per_step (optional).  The grid's state is unchanged.  The result is
+ * remembered for grids of the same precision, flag use and size in this
+ * process.  Needs 2 * state bytes of scratch device memory (ENOMEM otherwise). */
 lbt1_status lbt1_autotune(lbt1_grid *g, int32_t steps, int32_t reps, lbt1_kernel_config *best,
                           double *ms_per_step);
 

@@ -93,9 +93,11 @@ static const StepKernel kTable[] = {
     // two wavefronts per SIMD: FP64, and 16-bit storage with its codec, would
     // need scratch memory); four would need more registers than a wavefront has
     FUSED_ROWS(P_F32, 4, 3),
-    // taller strips: fewer redundant halo rows per stored row (FP32 at 30 rows
-    // measured slower than at 22)
-    FUSED(P_F32, 4, 22, 3),    FUSED(P_F32, 4, 22, 2),    FUSED_TALL(P_F16S, 2, 2),  FUSED_TALL(P_BF16S, 2, 2),
+    // taller strips: fewer redundant halo rows per stored row.  FP32 at 22 and 28
+    // rows: the runtime picks the height whose strip count best fills the last
+    // round of resident wavefronts (each with its two-step companion)
+    FUSED(P_F32, 4, 22, 3),    FUSED(P_F32, 4, 22, 2),    FUSED(P_F32, 4, 28, 3),    FUSED(P_F32, 4, 28, 2),
+    FUSED_TALL(P_F16S, 2, 2),  FUSED_TALL(P_BF16S, 2, 2),
     FUSED_ROWS(P_F64, 2, 2),   FUSED_ROWS(P_F32, 2, 2),   FUSED_ROWS(P_F32, 4, 2),
     FUSED_ROWS(P_F16S, 2, 2),  FUSED_ROWS(P_F16S, 4, 2),  FUSED_ROWS(P_BF16S, 2, 2),
     FUSED_ROWS(P_BF16S, 4, 2),

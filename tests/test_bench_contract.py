@@ -54,6 +54,12 @@ def test_counted_figures_need_matching_kernel_and_sources(tmp_path, monkeypatch)
     # another kernel, another storage format or other sources: no figure
     assert b.measured_traffic("f32", "k_step_fused<P_F32,4,14,3>", 0.5) is None
     assert b.measured_traffic("f16s", "k_step_fused<P_F32,4,22,3>", 0.5) is None
+    # several strip shapes of one storage format: each finds its own record
+    rec2 = dict(rec["f32"], kernel_bench="k_step_fused<P_F32,4,28,3>", traffic_ratio=1.12)
+    (prof / "traffic_periodic8192.json").write_text(json.dumps({"f32": [rec2, rec["f32"]]}))
+    assert b.measured_traffic("f32", "k_step_fused<P_F32,4,28,3>", 0.5)["ratio"] == 1.12
+    assert b.measured_traffic("f32", "k_step_fused<P_F32,4,22,3>", 0.5)["ratio"] == 1.25
+    assert b.measured_traffic("f32", "k_step_fused<P_F32,4,14,3>", 0.5) is None
     monkeypatch.setattr(b, "kernel_source_hash", lambda: "0" * 16)
     assert b.measured_traffic("f32", "k_step_fused<P_F32,4,22,3>", 0.5) is None
     assert b.measured_valu("f32", "k_step_fused<P_F32,4,22,3>") is None
@@ -64,5 +70,7 @@ def test_committed_profiles_match_the_sources():
     b = _bench()
     for name in ("traffic_periodic8192.json", "valu_periodic8192.json"):
         rec = json.load(open(os.path.join(ROOT, "profiles", name)))
-        for st, r in rec.items():
-            assert r["source_hash"] == b.kernel_source_hash(), (name, st)
+        for st, rs in rec.items():
+            for r in rs if isinstance(rs, list) else [rs]:
+                assert r["source_hash"] == b.kernel_source_hash(), (name, st, r["kernel_bench"])
+                assert b.profile_record(name, st, r["kernel_bench"]) == r

@@ -40,7 +40,7 @@ def test_fused_bitwise_equals_single_steps(prec, shape):
 
 
 @pytest.mark.parametrize("prec,vec,fuse,rows", [("f32", 2, 2, 14), ("f16s", 2, 2, 14), ("f32", 4, 3, 14),
-                                                ("f32", 4, 3, 22), ("f32", 4, 3, 6)])
+                                                ("f32", 4, 3, 22), ("f32", 4, 3, 28), ("f32", 4, 3, 6)])
 def test_fused_graph_bursts_and_splitting(prec, vec, fuse, rows):
     """Bursts (32 launches of two steps; 21 launches of three, which flip the parity),
     remainders (two-step launches after three-step ones, single steps) and split calls."""
@@ -117,7 +117,8 @@ def test_fused_refused_where_it_does_not_apply():
 
 
 @pytest.mark.parametrize("prec,vec,rows,fuse", [("f32", 4, 22, 2), ("f16s", 2, 22, 2), ("f16s", 2, 30, 2),
-                                                ("bf16s", 2, 30, 2), ("f32", 4, 22, 3)])
+                                                ("bf16s", 2, 30, 2), ("f32", 4, 22, 3), ("f32", 4, 28, 2),
+                                                ("f32", 4, 28, 3)])
 @pytest.mark.parametrize("shape", [(512, 77), (248, 33)])
 def test_tall_fused_strips_bitwise(prec, vec, rows, fuse, shape):
     """Strips taller than the single-step kernels: the remainder of 25 steps goes to
@@ -131,3 +132,37 @@ def test_tall_fused_strips_bitwise(prec, vec, rows, fuse, shape):
                       kernel=dict(kernel="strip", vec=vec, rows=rows, waves=waves, fuse=fuse))
         for a, b in zip(base, got):
             assert np.array_equal(a, b), waves
+
+
+@pytest.mark.parametrize("prec,kind", [("f32", "periodic"), ("f16s", "periodic"), ("f64", "cavity")])
+def test_autotune_leaves_the_state_and_the_trajectory_unchanged(prec, kind):
+    """The autotuner times its candidates on the grid's own memory: the state it
+    saved is restored bit for bit, and the steps after it give the bits of a grid
+    that was never tuned (every kernel family gives the same bits)."""
+    from paper_1912_09327_amd.grid import Grid
+    nx, ny = 520, 66
+    if kind == "periodic":
+        flags, per = None, 3
+        rho, jx, jy = _state(nx, ny, 71)
+    else:
+        flags, rho, jx, jy = I.cavity(nx, 0.05)[:4]
+        ny, per = nx, 0
+    ref = gpu_run(flags, rho, jx, jy, 37, prec, "paper", per, kernel=dict(kernel="gather"))
+    g = Grid(nx, ny, prec=prec, periodic=per)
+    try:
+        g.set_geometry(flags, rho, jx, jy)
+        before = g.read_moments()
+        g.step(5)
+        mid = g.read_moments()
+        cfg, _ = g.autotune(steps=12, reps=2)
+        after = g.read_moments()
+        for a, b in zip(mid, after):
+            assert np.array_equal(a, b)
+        g.step(32)
+        got = g.read_moments()
+    finally:
+        g.close()
+    assert cfg["kernel"] in (1, 2)
+    assert not all(np.array_equal(a, b) for a, b in zip(before, mid))
+    for a, b in zip(ref, got):
+        assert np.array_equal(a, b), cfg
