@@ -306,12 +306,12 @@ lbt1_kernel_config heuristic_config(int prec, bool haswall, int wall, int nx, in
                    : prec == LBT1_F32 ? (sx * ((ny + 21) / 22) >= 8L * cus ? 22 : 14) : 6;
       if (r == 22) {
         // three-step strips run two wavefronts per SIMD (8 per CU): a launch of W
-        // strips takes about ceil(W / slots) rounds of one strip's walk, 3 R + 6
-        // computed rows for R stored ones.  28 rows where that is no longer than
-        // at 22 (the 8192^2 field: 5 rounds of 90 rows against 7 of 72).
+        // strips takes about ceil(W / slots) rounds of one strip's walk, 3 R + 12
+        // stage-row emissions for R stored rows.  28 rows where that is no longer
+        // than at 22 (the 8192^2 field: 5 rounds of 96 against 7 of 78).
         const long slots = 8L * cus;
         const long w22 = sx * ((ny + 21) / 22), w28 = sx * ((ny + 27) / 28);
-        if ((w28 + slots - 1) / slots * 90 <= (w22 + slots - 1) / slots * 72) r = 28;
+        if ((w28 + slots - 1) / slots * 96 <= (w22 + slots - 1) / slots * 78) r = 28;
       }
       if (find_kernel(prec, false, 0, KIND_STRIP, v, r, k, false)) {
         c.vec = v;
