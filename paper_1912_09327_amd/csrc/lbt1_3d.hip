@@ -72,12 +72,19 @@ static const void *step3_kernel(int prec, int q, bool haswall, int wall) {
   return nullptr;
 }
 
-constexpr int kZChunk = 16;  // planes a tile block marches through
+// Planes a tile block marches through: 32 with 4- and 8-byte storage, 16 with
+// 16-bit storage (at 512^3, D3Q19: FP32 126.9k against 123.7k MLUPS at 16;
+// FP16S 131.0k against 137.1k at 32).
+template <int P>
+constexpr int zchunk_of() {
+  return P == P_F16S || P == P_BF16S ? 16 : 32;
+}
+static int zchunk_for(int prec) { return prec == P_F16S || prec == P_BF16S ? 16 : 32; }
 constexpr int kTile3Y = 8;   // rows of a tile block (64 x 8 nodes, 512 threads)
 
 static const void *tile3_kernel(int prec, int q) {
 #define T3(P, Q) \
-  if (prec == P && q == Q) return (const void *)&k_step3_tile<P, Q, kZChunk, kTile3Y>;
+  if (prec == P && q == Q) return (const void *)&k_step3_tile<P, Q, zchunk_of<P>(), kTile3Y>;
   T3(P_F64, 19) T3(P_F64, 27) T3(P_F32, 19) T3(P_F32, 27) T3(P_F16S, 19) T3(P_F16S, 27) T3(P_BF16S, 19)
   T3(P_BF16S, 27)
 #undef T3
@@ -339,7 +346,7 @@ lbt1_status lbt1_grid3d_step(lbt1_grid3d *g, int64_t n) {
   if ((e = hipSetDevice(g->device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
   const dim3 block = g->tile ? dim3(64 * kTile3Y, 1, 1) : dim3(64, 4, 1);
   const dim3 grid = g->tile ? dim3((g->nx + kTile3X - 1) / kTile3X, (g->ny + kTile3Y - 1) / kTile3Y,
-                                   (g->nz + kZChunk - 1) / kZChunk)
+                                   (g->nz + zchunk_for(g->prec) - 1) / zchunk_for(g->prec))
                             : dim3((g->nx + 63) / 64, (g->ny + 3) / 4, g->nz);
   for (int64_t s = 0; s < n; ++s) {
     Step3Args a = step3_args(g, g->parity);
