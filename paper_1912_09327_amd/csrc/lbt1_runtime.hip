@@ -1280,7 +1280,8 @@ lbt1_status lbt1_autotune(lbt1_grid *g, int32_t steps, int32_t reps, lbt1_kernel
       }
     }
   }
-  drop_bursts(&t);
+  hipStreamSynchronize(g->stream);
+  drop_bursts(&t);  // (the clone's bursts, idle now)
   const hipError_t er = hipMemcpyAsync(g->base, p, 2 * g->L.state, hipMemcpyDeviceToDevice, g->stream);
   hipStreamSynchronize(g->stream);
   hipEventDestroy(e0);
