@@ -225,7 +225,8 @@ typedef struct {
                      periodic in x; otherwise the last chunk of a row may run into the
                      row padding, which reads as SOLID like the outside of the axis */
   int32_t rows;   /* STRIP: rows per strip, 6 or 14 (fused kernels also 22; 28 for three
-                     FP32 steps, 30 for 16-bit storage; two steps on grids with walls also 2; lbt1_set_kernel
+                     FP32 steps, 30 for 16-bit storage; two steps on grids with walls also 2,
+                     and 30 except in FP64; lbt1_set_kernel
                      says EINVAL for a shape that is not built) */
   int32_t waves;  /* STRIP: resident wavefronts per CU the launch aims at (1..32);
                      0 = one wavefront per strip, no grid-stride loop */
@@ -234,7 +235,8 @@ typedef struct {
                      once per pass, results bit for bit those of single steps);
                      fuse <= vec.  3: vec 4, FP32, grids periodic in x and y without
                      SOLID or FIXED nodes.  2: any grid that is not multiphase (with
-                     walls, fixed nodes or open axes: vec 2, rows 2, 6 or 14).  Step counts that are not a
+                     walls, fixed nodes or open axes: vec 2, rows 2, 6, 14, or 30
+                     except in FP64).  Step counts that are not a
                      multiple of fuse end with two-step launches of the same strip
                      shape (after three-step ones), else single-step launches of the
                      same height, else the gather kernel. */

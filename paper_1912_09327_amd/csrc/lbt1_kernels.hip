@@ -58,6 +58,9 @@ __global__ void __launch_bounds__(64) k_reduce_final(const double *partials, int
 #define FUSED_WALL_ALL(P)                                                                       \
   FUSED_WALL(P, 0, 2, 2), FUSED_WALL(P, 0, 2, 6), FUSED_WALL(P, 0, 2, 14), FUSED_WALL(P, 1, 2, 2), \
       FUSED_WALL(P, 1, 2, 6), FUSED_WALL(P, 1, 2, 14)
+// 30 rows: fewer rounds of resident wavefronts on the largest grids (FP64 at 30
+// rows would spill a scalar register)
+#define FUSED_WALL_TALL(P) FUSED_WALL(P, 0, 2, 30), FUSED_WALL(P, 1, 2, 30)
 #define FUSED_TALL(P, V, K) FUSED(P, V, 22, K), FUSED(P, V, 30, K)
 #define STRIP_WALLS(P, V, R) STRIP(P, false, 0, V, R), STRIP(P, true, 0, V, R), STRIP(P, true, 1, V, R)
 #define STRIP_ROWS(P, V) STRIP_WALLS(P, V, 6), STRIP_WALLS(P, V, 14)
@@ -102,6 +105,7 @@ static const StepKernel kTable[] = {
     FUSED_ROWS(P_F16S, 2, 2),  FUSED_ROWS(P_F16S, 4, 2),  FUSED_ROWS(P_BF16S, 2, 2),
     FUSED_ROWS(P_BF16S, 4, 2),
     FUSED_WALL_ALL(P_F64), FUSED_WALL_ALL(P_F32), FUSED_WALL_ALL(P_F16S), FUSED_WALL_ALL(P_BF16S),
+    FUSED_WALL_TALL(P_F32), FUSED_WALL_TALL(P_F16S), FUSED_WALL_TALL(P_BF16S),
     BGK_ALL(P_F64), BGK_ALL(P_F32), BGK_ALL(P_F16S), BGK_ALL(P_BF16S),
     SC_ALL(P_F64, 2),  SC_ALL(P_F32, 2),  SC_STRIP(P_F32, 4, 6), SC_STRIP(P_F32, 4, 14),
     SC_FUSED(P_F32, 4, 6), SC_FUSED(P_F32, 4, 14),

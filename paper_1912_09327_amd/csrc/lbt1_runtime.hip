@@ -328,9 +328,22 @@ lbt1_kernel_config heuristic_config(int prec, bool haswall, int wall, int nx, in
     // every size, in FP64 at 256 and 4096 and within 6 % at 1024).  Strip height:
     // up to 512 x 512 nodes 2 rows (the step is bound by the latency of a strip's
     // walk: 2.9 us against 5.0 at 6 rows on a 256^2 cavity), else 14 where there
-    // are enough strips, else 6
+    // are enough strips, else 6.  30 rows where a launch then takes at least 5 %
+    // less of rounds of resident wavefronts times walk length (2 R + 6 stage rows)
+    // than at 14: on the 8192^2 cavity 6 rounds of 66 against 13 of 34 (FP32 0.190
+    // against 0.204 ms per step); at 4096^2 2 of 66 against 4 of 34, and 14 rows
+    // are 1-4 % faster.
     const long sx = (chunks_of(nx, 2) + 61) / 62;
-    const int r = (long)nx * ny <= 512L * 512 ? 2 : sx * ((ny + 13) / 14) >= 8L * cus ? 14 : 6;
+    int r = (long)nx * ny <= 512L * 512 ? 2 : sx * ((ny + 13) / 14) >= 8L * cus ? 14 : 6;
+    const StepKernel *k30 = find_kernel(prec, true, wall, KIND_STRIP, 2, 30, 2, false);
+    if (r == 14 && k30) {
+      int per_cu = 0;  // 256-thread blocks per CU
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k30->fn, 256, 0) == hipSuccess && per_cu > 0) {
+        const long slots = 4L * per_cu * cus;
+        const long w14 = sx * ((ny + 13) / 14), w30 = sx * ((ny + 29) / 30);
+        if ((w30 + slots - 1) / slots * 66 * 20 < (w14 + slots - 1) / slots * 34 * 19) r = 30;
+      }
+    }
     if (find_kernel(prec, true, wall, KIND_STRIP, 2, r, 2, false)) {
       c.vec = 2;
       c.rows = r;

@@ -16,6 +16,8 @@ from paper_1912_09327_amd import inputs as I
 pytestmark = pytest.mark.gpu
 
 GATHER = dict(kernel="gather")
+# strip heights built for two fused steps with walls (30 rows not in FP64)
+ROWS = {"f64": (2, 6, 14), "f32": (2, 6, 14, 30), "f16s": (2, 6, 14, 30), "bf16s": (2, 6, 14, 30)}
 
 
 def _case(kind, nx, ny, seed):
@@ -51,7 +53,7 @@ def test_fused_wall_bitwise_equals_single_steps(prec, kind, wall):
         flags, rho, jx, jy, per = _case(kind, nx, ny, nx * 7 + ny)
         F = (1e-5, -2e-6)
         base = gpu_run(flags, rho, jx, jy, 25, prec, wall, per, F, kernel=GATHER)
-        for rows in (2, 6, 14):
+        for rows in ROWS[prec]:
             for waves in (0, 8):
                 cfg = dict(kernel="strip", vec=2, rows=rows, waves=waves, fuse=2)
                 got = gpu_run(flags, rho, jx, jy, 25, prec, wall, per, F, kernel=cfg)
@@ -128,7 +130,7 @@ def test_fused_wall_thin_grids(prec, shape, kind):
         flags, rho, jx, jy, per = _case(kind, nx, ny, nx + 3 * ny)
     F = (1e-5, 3e-6)
     base = gpu_run(flags, rho, jx, jy, 13, prec, "halfway", per, F, kernel=GATHER)
-    for rows in (2, 6, 14):
+    for rows in ROWS[prec]:
         got = gpu_run(flags, rho, jx, jy, 13, prec, "halfway", per, F,
                       kernel=dict(kernel="strip", vec=2, rows=rows, waves=0, fuse=2))
         for a, b in zip(base, got):
