@@ -195,7 +195,7 @@ def test_sc_fused_bitwise_equals_gather(shape):
     nx, ny = shape
     flags, rho, jx, jy, per = _case("periodic", nx, ny, 6)
     base, _ = _gpu(flags, rho, jx, jy, 25, "f32", "paper", per, (1e-5, 0.0), kernel=dict(kernel="gather"))
-    for rows in (6, 14):
+    for rows in (6, 14, 22):
         for waves in (0, 8):
             got, name = _gpu(flags, rho, jx, jy, 25, "f32", "paper", per, (1e-5, 0.0),
                              kernel=dict(kernel="strip", vec=4, rows=rows, waves=waves, fuse=2))
@@ -204,7 +204,8 @@ def test_sc_fused_bitwise_equals_gather(shape):
                 assert np.array_equal(a, b), (rows, waves)
 
 
-def test_sc_fused_bursts_and_splitting():
+@pytest.mark.parametrize("rows", [14, 22])
+def test_sc_fused_bursts_and_splitting(rows):
     from paper_1912_09327_amd.grid import Grid
     nx, ny = 372, 90
     flags, rho, jx, jy, per = _case("periodic", nx, ny, 7)
@@ -212,7 +213,7 @@ def test_sc_fused_bursts_and_splitting():
     g = Grid(nx, ny, prec="f32", periodic=per, multiphase=SC)
     try:
         g.set_geometry(flags, rho, jx, jy)
-        g.set_kernel("strip", vec=4, rows=14, waves=0, fuse=2)
+        g.set_kernel("strip", vec=4, rows=rows, waves=0, fuse=2)
         for n in (1, 64, 3, 128, 21, 2, 4, 5, 1, 2):
             g.step(n)
         got = g.read_moments()
