@@ -1,15 +1,15 @@
 """GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
 
 Bars (see gpu_helpers): the state (rho, jx, jy) within 1e-12 (FP64) and 1e-5
-(FP32) normwise relative, momentum alone within 1e-10 / 1e-4 of the run's
-largest momentum; FP16/BF16 shifted storage within 8 ulp of the field's
-largest magnitude.  Kernel families and launch shapes agree bit for bit.
+(FP32) normwise relative, momentum alone within 1e-12 / 1e-5 of the oracle's
+largest momentum (1e-10 / 1e-4 for the named long runs only); FP16/BF16 shifted
+storage within 8 ulp of the field's largest magnitude.  Kernel families and launch shapes agree bit for bit.
 """
 import numpy as np
 import pytest
 
 import oracle
-from gpu_helpers import JTOL, TOL, field_errors, gpu_run, oracle_run, reduced_bar
+from gpu_helpers import JTOL, LONG_JTOL, TOL, field_errors, gpu_run, oracle_run, reduced_bar
 from paper_1912_09327_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
@@ -168,7 +168,9 @@ def test_channel_64x32_f64_10000_steps(wall):
     ref = oracle_run(flags, one, zero, zero, 10000, wall, per, (1e-6, 0.0))
     got = gpu_run(flags, one, zero, zero, 10000, "f64", wall, per, (1e-6, 0.0))
     ex, ej = field_errors(got, ref, flags)
-    assert ex <= TOL["f64"] and ej <= JTOL["f64"], (ex, ej)
+    # a named long run: the oracle's own rounding drift over 10,000 steps (measured
+    # 6.8e-13 paper, 5.5e-12 half-way) is above the 1e-12 bar of short runs
+    assert ex <= TOL["f64"] and ej <= LONG_JTOL["f64"], (ex, ej)
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
@@ -179,7 +181,8 @@ def test_cavity_256_matches_oracle(prec):
     ref = oracle_run(flags, rho, jx, jy, 3000, "paper", per)
     got = gpu_run(flags, rho, jx, jy, 3000, prec, "paper", per)
     ex, ej = field_errors(got, ref, flags)
-    assert ex <= TOL[prec] and ej <= JTOL[prec], (ex, ej)
+    # a named long run (measured: FP32 1.7e-5 of max |j| after 3,000 steps)
+    assert ex <= TOL[prec] and ej <= LONG_JTOL[prec], (ex, ej)
 
 
 def test_codec_round_trip_and_rounding():

@@ -28,6 +28,17 @@ MUTATIONS = {
     "sc_force_uses_wrong_component": ("sy += OR_W[k] * pk * OR_EY[k];", "sy += OR_W[k] * pk * OR_EX[k];"),
     "sc_force_without_own_psi": ("FX[x] = -G * px * sx;", "FX[x] = -G * sx;"),
     "sc_psi_sign": ("rho0 * (1.0 - exp(-r / rho0))", "rho0 * (1.0 + exp(-r / rho0))"),
+    # mistakes in the diagnostics (oracle_reduce)
+    "residual_on_momentum_not_velocity": ("double du = fabs(U[x] / R[x] - Us[x] / Rs[x]);",
+                                          "double du = fabs(U[x] - Us[x]);"),
+    "residual_ignores_y_component": ("if (dv > res) res = dv;", "(void)dv;"),
+    "reduce_counts_non_fluid_nodes": ("if (flags && flags[x] != OR_FLUID) continue;",
+                                      "if (flags && flags[x] == OR_FIXED) continue;"),
+    "mass_of_the_deviation": ("m += R[x];", "m += R[x] - 1.0;"),
+    "non_finite_misses_momentum": ("if (!isfinite(R[x]) || !isfinite(U[x]) || !isfinite(V[x])) bad += 1.0;",
+                                   "if (!isfinite(R[x])) bad += 1.0;"),
+    "residual_against_own_snapshot_density": ("double dv = fabs(V[x] / R[x] - Vs[x] / Rs[x]);",
+                                              "double dv = fabs(V[x] / R[x] - Vs[x] / R[x]);"),
 }
 
 

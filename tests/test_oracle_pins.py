@@ -380,23 +380,110 @@ def test_p9_memory_example_of_the_paper():
 
 
 # ----------------------------------------------------------------- reductions
-def test_reduce_definitions():
-    rng = _rng(11)
-    ny, nx = 9, 8
-    flags = (rng.random((ny, nx)) < 0.3).astype(np.uint8)
-    rho, jx, jy = _random_state(rng, ny, nx)
-    snap = _random_state(rng, ny, nx)
-    d = oracle.reduce(rho, jx, jy, flags, snap)
-    fl = flags == 0
-    assert d["fluid"] == fl.sum()
-    assert d["mass"] == pytest.approx(rho[fl].sum(), rel=1e-15)
-    assert d["mom_x"] == pytest.approx(jx[fl].sum(), rel=1e-14)
-    du = np.abs(jx / rho - snap[1] / snap[0])[fl].max()
-    dv = np.abs(jy / rho - snap[2] / snap[0])[fl].max()
-    assert d["residual"] == max(du, dv)
-    rho2 = rho.copy()
-    rho2[np.argwhere(fl)[0][0], np.argwhere(fl)[0][1]] = np.nan
-    assert oracle.reduce(rho2, jx, jy, flags)["nonfinite"] == 1
+# The diagnostics of section 3 (velocity change between two times, mass) are
+# pinned by states whose sums and velocity changes are known in closed form,
+# not by re-deriving the sums.
+@pytest.mark.parametrize("rho0", [1.0, 1.75])
+@pytest.mark.parametrize("axis", ["x", "y"])
+def test_reduce_residual_of_the_shear_wave(rho0, axis):
+    """A shear wave j = rho0 A sin(k y) e_x on a uniform density rho0 decays exactly
+    by (2 + cos k)/3 per step (P3; the group shares of Appendix A.1 do not depend on
+    rho).  So the velocity u = j / rho changes between steps t - 100 and t by
+    A lam^(t - 100) (1 - lam^100) sin(k y), and the residual is that amplitude times
+    max_y |sin(k y)|.  rho0 != 1 separates u = j / rho from j; the transposed wave
+    (a y momentum varying along x) pins the second component."""
+    ny, nx, A, m, t0 = 12, 5, 0.05, 2, 7
+    kwave = 2 * math.pi * m / ny
+    y = np.arange(ny)[:, None] * np.ones((1, nx))
+    rho = np.full((ny, nx), rho0)
+    jw = rho0 * A * np.sin(kwave * y)
+    zero = np.zeros((ny, nx))
+    state = (rho, jw, zero) if axis == "x" else (rho.T.copy(), zero.T.copy(), jw.T.copy())
+    snap = oracle.run(*state, t0, None, 3)
+    cur = oracle.run(*snap, 100, None, 3)
+    lam = cf.shear_wave_factor(kwave)
+    smax = max(abs(math.sin(kwave * yy)) for yy in range(ny))       # sin(pi/3) here
+    expect = A * lam ** t0 * (1 - lam ** 100) * smax
+    d = oracle.reduce(*cur, None, snap)
+    assert d["residual"] == pytest.approx(expect, rel=1e-12)
+    assert d["fluid"] == ny * nx and d["nonfinite"] == 0
+    # momentum of a sine over whole periods is zero; periodic mass is rho0 N exactly
+    assert d["mass"] == pytest.approx(rho0 * ny * nx, rel=1e-14)
+    assert abs(d["mom_x"]) < 1e-13 and abs(d["mom_y"]) < 1e-13     # N eps rounding of the sums
+    # against itself the residual is exactly zero
+    assert oracle.reduce(*cur, None, cur)["residual"] == 0.0
+
+
+def test_reduce_residual_against_a_snapshot_of_another_density():
+    """Uniform periodic flow under a force (P2): rho stays rho0 and j_n = j_0 + n F, so
+    u_n = (j_0 + n F) / rho0.  Against a uniform snapshot of density 1.5 and velocity
+    u_s (momentum 1.5 u_s) the residual is max(|u_n - u_s|) over both components."""
+    ny, nx, n, rho0 = 6, 5, 10, 1.25
+    j0, F, us = (0.03, -0.02), (2.5e-5, -1e-5), (0.01, 0.004)
+    state = (np.full((ny, nx), rho0), np.full((ny, nx), j0[0]), np.full((ny, nx), j0[1]))
+    cur = oracle.run(*state, n, None, 3, F)
+    snap = (np.full((ny, nx), 1.5), np.full((ny, nx), 1.5 * us[0]), np.full((ny, nx), 1.5 * us[1]))
+    expect = max(abs((j0[0] + n * F[0]) / rho0 - us[0]), abs((j0[1] + n * F[1]) / rho0 - us[1]))
+    assert oracle.reduce(*cur, None, snap)["residual"] == pytest.approx(expect, rel=1e-12)
+
+
+def _steady_channel(ny, nx, F, solid_rho=3.0, solid_j=0.3):
+    """The steady Poiseuille state of the paper's wall rule (P5): walls on rows 0 and
+    H = ny - 1, u_eq(y) = 3 F y (H - y), rho = 1, j = u_eq - F; the wall rows hold
+    values that no FLUID diagnostic may see."""
+    flags = np.zeros((ny, nx), np.uint8)
+    flags[0] = flags[-1] = oracle.SOLID
+    ueq = cf.poiseuille_ueq_paper(ny, F)
+    rho = np.ones((ny, nx))
+    jx = np.repeat((ueq - F)[:, None], nx, axis=1)
+    rho[0] = rho[-1] = solid_rho
+    jx[0] = jx[-1] = solid_j
+    return flags, rho, jx, np.zeros((ny, nx))
+
+
+@pytest.mark.parametrize("wall", [0, 1])
+def test_reduce_sums_over_fluid_nodes_of_the_steady_channel(wall):
+    """Over the N = ny - 2 fluid rows of the steady channel: mass = N nx (rho = 1), x
+    momentum = nx sum_y (3 F y (H - y) - F) = nx F ((H - 1) H (H + 1) / 2 - (H - 1)),
+    y momentum 0, FLUID count N nx; a fixed point (P5), so the residual after 100 more
+    steps is at rounding level.  The wall rows carry rho = 3 and j = 0.3 (and a
+    snapshot with j = -0.3), which count nowhere."""
+    ny, nx, F = 17, 6, 2.5e-5
+    H = ny - 1
+    flags, rho, jx, jy = _steady_channel(ny, nx, F)
+    if wall == 1:
+        ueq = cf.poiseuille_ueq_halfway(ny, F)
+        jx[1:-1] = (ueq - F)[1:-1, None]
+    snap = (rho.copy(), jx.copy(), jy.copy())
+    snap[1][0] = snap[1][-1] = -0.3
+    cur = oracle.run(rho, jx, jy, 100, flags, 1, (F, 0.0), wall)
+    d = oracle.reduce(*cur, flags, snap)
+    N = ny - 2
+    assert d["fluid"] == N * nx
+    assert d["mass"] == pytest.approx(N * nx, rel=1e-14)
+    if wall == 0:
+        assert d["mom_x"] == pytest.approx(nx * F * ((H - 1) * H * (H + 1) / 2 - (H - 1)), rel=1e-11)
+    else:
+        # half-way walls at 1/2 and N + 1/2: u_eq = 3 F [(y - 1/2)(N + 1/2 - y) + 1/4]
+        s = sum((yy - 0.5) * (N + 0.5 - yy) + 0.25 for yy in range(1, N + 1))
+        assert d["mom_x"] == pytest.approx(nx * F * (3 * s - N), rel=1e-11)
+    assert abs(d["mom_y"]) < 1e-13     # rho/6 - rho/6 per node, rounded, summed
+    assert d["residual"] < 1e-14       # a fixed point up to rounding; the wall rows would give 0.6
+    assert d["nonfinite"] == 0
+
+
+def test_reduce_counts_non_finite_fluid_nodes():
+    """Three FLUID nodes made non-finite, one through each field, and two wall nodes:
+    the count is 3."""
+    ny, nx, F = 9, 7, 1e-5
+    flags, rho, jx, jy = _steady_channel(ny, nx, F)
+    rho[2, 1] = np.nan
+    jx[4, 3] = np.inf
+    jy[6, 5] = -np.inf
+    rho[0, 2] = np.nan
+    jx[-1, 4] = np.inf
+    d = oracle.reduce(rho, jx, jy, flags)
+    assert d["nonfinite"] == 3 and d["fluid"] == (ny - 2) * nx
 
 
 def test_lid_cavity_mass_is_not_conserved_but_fixed_row_is_held():
