@@ -178,6 +178,11 @@ __device__ __forceinline__ void finish(C sm, C xm, C s0, C x0, C sp, C xp, C &d,
 }
 
 // ----------------------------------------------------------------- kernel arguments
+// Bytes of the trash area per moment field.  Lane l of a wavefront redirects a
+// store of VEC values to element l * VEC of a field's region, so every kernel
+// asserts 64 * VEC * sizeof(stored value) <= kTrashRegion.
+constexpr long kTrashRegion = 1024;
+
 struct StepArgs {
   const void *src[3];  // d, jx, jy planes of the current parity
   void *dst[3];        // planes of the next parity
@@ -190,8 +195,9 @@ struct StepArgs {
   double fx, fy;       // body force
   double sc_d, sc_j;   // decode scales (stored * sc = value)
   double is_d, is_j;   // encode scales (value * is = stored)
-  void *trash;         // 3 KiB of device scratch: target of the stores of lanes and
-                       // rows outside the grid, so that stores need no branch
+  void *trash;         // 3 KiB of device scratch, one kTrashRegion per moment field:
+                       // target of the stores of lanes and rows outside the grid, so
+                       // that stores need no branch
   double sc_G, sc_rho0;  // multiphase kernels: Shan-Chen coupling and psi scale
 };
 

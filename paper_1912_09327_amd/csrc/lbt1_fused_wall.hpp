@@ -251,7 +251,8 @@ __device__ __forceinline__ void fused_wall_body(const StepArgs &a, const int chu
     const bool ok = t < ny && lane_out;
     const long idx = (long)t * rs + xc;
     S *trash = static_cast<S *>(a.trash) + lane * VEC;
-    const long tq = 1024 / sizeof(S);
+    const long tq = kTrashRegion / sizeof(S);
+    static_assert(64 * VEC * sizeof(S) <= kTrashRegion, "a wavefront's redirected stores fit one trash region");
     *reinterpret_cast<SP *>(ok ? d0p + idx : trash) = out[0];
     *reinterpret_cast<SP *>(ok ? d1p + idx : trash + tq) = out[1];
     *reinterpret_cast<SP *>(ok ? d2p + idx : trash + 2 * tq) = out[2];

@@ -108,8 +108,8 @@ Layout layout_of(int nx, int ny, int prec, uint32_t options) {
   off += round_up((size_t)L.nparts * 6 * sizeof(double), 256);
   L.out_off = off;
   off += 256;
-  L.trash_off = off;  // 3 KiB: stores of lanes / rows outside the grid land here
-  off += 3 * 1024;
+  L.trash_off = off;  // 3 KiB: stores of lanes / rows outside the grid land here (one region per field)
+  off += 3 * kTrashRegion;
   L.total = off;
   return L;
 }
