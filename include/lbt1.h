@@ -197,6 +197,22 @@ lbt1_status lbt1_read_populations(lbt1_grid *g, double *f);
  * out[5].  Synchronises the grid's stream. */
 lbt1_status lbt1_reduce(lbt1_grid *g, uint32_t what, double *out);
 
+/* lbt1_reduce for callers that cannot allocate (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): the same diagnostics,
+ * enqueued on the grid's stream without synchronising and without allocating
+ * anything.  The partial sums go to a static device array of the library
+ * (1024 rows of six doubles, 48 KiB per device, held until the process ends)
+ * instead of the grid's workspace; every grid size fits, since the partial
+ * count is capped at 1024 (EINVAL otherwise).  `out` is caller-owned
+ * device-accessible memory of LBT1_REDUCE_SLOTS doubles, written when the
+ * stream reaches this work, with the slots of lbt1_reduce (those not asked for
+ * untouched except out[5]); results are bitwise those of lbt1_reduce.  With
+ * LBT1_REDUCE_RESIDUAL the snapshot is refreshed as by lbt1_reduce.  The
+ * static array is shared by all calls on one device: calls whose work overlaps
+ * on the device (grids on different streams) race and must be ordered by the
+ * caller. */
+lbt1_status lbt1_reduce_noalloc(lbt1_grid *g, uint32_t what, double *out);
+
 /* Wait until all work enqueued on the grid's stream has finished. */
 lbt1_status lbt1_sync(lbt1_grid *g);
 

@@ -85,6 +85,7 @@ SIGNATURES = {
     "lbt1_read_window": (ctypes.c_int, [_vp, _i32, _i32, _i32, _i32, _dp, _dp, _dp]),
     "lbt1_read_populations": (ctypes.c_int, [_vp, _dp]),
     "lbt1_reduce": (ctypes.c_int, [_vp, ctypes.c_uint32, _dp]),
+    "lbt1_reduce_noalloc": (ctypes.c_int, [_vp, ctypes.c_uint32, _vp]),
     "lbt1_sync": (ctypes.c_int, [_vp]),
     "lbt1_destroy_grid": (ctypes.c_int, [_vp]),
     "lbt1_last_error": (ctypes.c_char_p, []),

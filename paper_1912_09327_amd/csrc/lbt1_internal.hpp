@@ -21,6 +21,7 @@ struct StepKernel {
 const StepKernel *step_kernels(int *count);
 const void *reduce_partial_kernel(int prec);
 const void *reduce_final_kernel();
+const void *reduce_final_out_kernel();  // final pass writing the user-facing slots
 const void *bgk_reduce_partial_kernel(int prec);
 const void *bgk_psi_kernel(int prec);
 const void *batch_step_kernel(int prec, int vec_class, int rows);

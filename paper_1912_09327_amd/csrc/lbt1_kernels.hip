@@ -10,11 +10,11 @@
 namespace lbt1 {
 
 // one wavefront: lane l combines partial rows l, l + 64, ... in index order, then
-// a fixed butterfly over the lanes; lane 0 writes out[6] (slot 3 is a maximum, the
-// others sums)
-__global__ void __launch_bounds__(64) k_reduce_final(const double *partials, int nparts, double *out) {
+// a fixed butterfly over the lanes (slot 3 is a maximum, the others sums)
+__device__ __forceinline__ void reduce_rows(const double *partials, int nparts, double (&acc)[6]) {
   const int l = threadIdx.x;
-  double acc[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+  for (int q = 0; q < 6; ++q) acc[q] = 0.0;
   for (int b = l; b < nparts; b += 64) {
 #pragma unroll
     for (int q = 0; q < 6; ++q) {
@@ -30,9 +30,35 @@ __global__ void __launch_bounds__(64) k_reduce_final(const double *partials, int
       acc[q] = q == 3 ? __builtin_fmax(acc[q], o) : acc[q] + o;
     }
   }
-  if (l == 0) {
+}
+
+// lane 0 writes the six raw slots (0 sum of rho - 1, 1-2 momentum, 3 residual,
+// 4 non-finite count, 5 FLUID count)
+__global__ void __launch_bounds__(64) k_reduce_final(const double *partials, int nparts, double *out) {
+  double acc[6];
+  reduce_rows(partials, nparts, acc);
+  if (threadIdx.x == 0) {
 #pragma unroll
     for (int q = 0; q < 6; ++q) out[q] = acc[q];
+  }
+}
+
+// The same combination, written as lbt1_reduce reports it: slot 0 the mass
+// (FLUID count + sum of rho - 1, the same FP64 addition the host makes), the
+// slots of `what` (LBT1_REDUCE_* bits), and slot 5 always.
+__global__ void __launch_bounds__(64) k_reduce_final_out(const double *partials, int nparts, uint32_t what,
+                                                         double *out) {
+  double acc[6];
+  reduce_rows(partials, nparts, acc);
+  if (threadIdx.x == 0) {
+    if (what & 1u) out[0] = acc[5] + acc[0];
+    if (what & 2u) {
+      out[1] = acc[1];
+      out[2] = acc[2];
+    }
+    if (what & 4u) out[3] = acc[3];
+    if (what & 8u) out[4] = acc[4];
+    out[5] = acc[5];
   }
 }
 
@@ -129,6 +155,8 @@ const void *reduce_partial_kernel(int prec) {
 }
 
 const void *reduce_final_kernel() { return (const void *)&k_reduce_final; }
+
+const void *reduce_final_out_kernel() { return (const void *)&k_reduce_final_out; }
 
 const void *bgk_psi_kernel(int prec) {
   switch (prec) {

@@ -661,64 +661,99 @@ lbt1_status enqueue_steps(lbt1_grid *g, int64_t n, hipStream_t s, bool use_graph
   return LBT1_OK;
 }
 
-static lbt1_status enqueue_reduce_pop(lbt1_grid *g, uint32_t what, hipStream_t s) {
-  BgkReduceArgs a{};
-  for (int q = 0; q < 9; ++q) a.cur[q] = g->plane[g->parity][q];
-  for (int q = 0; q < 3; ++q) a.snap[q] = g->snap[q];
-  a.flags = g->haswall ? g->flags : nullptr;
-  a.nx = g->nx;
-  a.ny = g->ny;
-  a.pitch = g->L.pitch;
-  a.rs = g->L.rs;
-  a.snap_rs = g->L.snap_rs;
-  a.sc = g->sc[0];
-  a.sc_d = g->sc[0];
-  a.sc_j = g->sc[1];
-  a.is_d = 1.0 / g->sc[0];
-  a.is_j = 1.0 / g->sc[1];
-  a.what = what;
-  a.partials = g->partials;
+// Number of partial rows (reduction blocks) the partial pass of grid g writes.
+static int reduce_blocks(const lbt1_grid *g) {
   const long n = (long)g->nx * g->ny;
-  const int blocks = (int)std::min<long>(g->L.nparts, std::max<long>(1, (n + 1023) / 1024));
-  void *args[] = {&a};
-  hipError_t e = hipLaunchKernel(bgk_reduce_partial_kernel(g->prec), dim3(blocks), dim3(256), args, 0, s);
+  return (int)std::min<long>(g->L.nparts, std::max<long>(1, (n + 1023) / 1024));
+}
+
+// The two reduction passes of grid g on stream s: block partials into
+// `partials` (reduce_blocks(g) rows of six doubles), then one wavefront combines
+// them into `out`: the six raw slots, or with user_slots the slots as
+// lbt1_reduce reports them (k_reduce_final_out).
+static lbt1_status enqueue_reduce_into(lbt1_grid *g, uint32_t what, hipStream_t s, double *partials, double *out,
+                                       bool user_slots) {
+  const int blocks = reduce_blocks(g);
+  hipError_t e;
+  if (g->pop) {
+    BgkReduceArgs a{};
+    for (int q = 0; q < 9; ++q) a.cur[q] = g->plane[g->parity][q];
+    for (int q = 0; q < 3; ++q) a.snap[q] = g->snap[q];
+    a.flags = g->haswall ? g->flags : nullptr;
+    a.nx = g->nx;
+    a.ny = g->ny;
+    a.pitch = g->L.pitch;
+    a.rs = g->L.rs;
+    a.snap_rs = g->L.snap_rs;
+    a.sc = g->sc[0];
+    a.sc_d = g->sc[0];
+    a.sc_j = g->sc[1];
+    a.is_d = 1.0 / g->sc[0];
+    a.is_j = 1.0 / g->sc[1];
+    a.what = what;
+    a.partials = partials;
+    void *args[] = {&a};
+    e = hipLaunchKernel(bgk_reduce_partial_kernel(g->prec), dim3(blocks), dim3(256), args, 0, s);
+  } else {
+    ReduceArgs a{};
+    for (int q = 0; q < 3; ++q) {
+      a.cur[q] = g->plane[g->parity][q];
+      a.snap[q] = g->snap[q];
+    }
+    a.flags = g->haswall ? g->flags : nullptr;
+    a.nx = g->nx;
+    a.ny = g->ny;
+    a.pitch = g->L.pitch;
+    a.rs = g->L.rs;
+    a.sc_d = g->sc[0];
+    a.sc_j = g->sc[1];
+    a.what = what;
+    a.partials = partials;
+    void *args[] = {&a};
+    e = hipLaunchKernel(reduce_partial_kernel(g->prec), dim3(blocks), dim3(256), args, 0, s);
+  }
   if (e != hipSuccess) return hip_fail(e, "reduce launch");
-  const double *parts = g->partials;
+  const double *parts = partials;
   int np = blocks;
-  double *out = g->red_out;
-  void *args2[] = {&parts, &np, &out};
-  e = hipLaunchKernel(reduce_final_kernel(), dim3(1), dim3(64), args2, 0, s);
+  if (user_slots) {
+    void *args2[] = {&parts, &np, &what, &out};
+    e = hipLaunchKernel(reduce_final_out_kernel(), dim3(1), dim3(64), args2, 0, s);
+  } else {
+    void *args2[] = {&parts, &np, &out};
+    e = hipLaunchKernel(reduce_final_kernel(), dim3(1), dim3(64), args2, 0, s);
+  }
   if (e != hipSuccess) return hip_fail(e, "reduce launch");
   return LBT1_OK;
 }
 
 lbt1_status enqueue_reduce(lbt1_grid *g, uint32_t what, hipStream_t s) {
-  if (g->pop) return enqueue_reduce_pop(g, what, s);
-  ReduceArgs a{};
-  for (int q = 0; q < 3; ++q) {
-    a.cur[q] = g->plane[g->parity][q];
-    a.snap[q] = g->snap[q];
+  return enqueue_reduce_into(g, what, s, g->partials, g->red_out, false);
+}
+
+// ----------------------------------------------------------------- allocation-free reduction
+// Partial rows of lbt1_reduce_noalloc, in a file-scope device array instead of
+// the grid's workspace: kReduceBlocks rows of six doubles (48 KiB on every
+// device the library runs on, held until the process ends).  In host code the
+// name `scratch` is only a stand-in for the symbol; its device address comes
+// from hipGetSymbolAddress, once per device, and only that address is used.
+constexpr int kScratchRows = kReduceBlocks;
+static __device__ __align__(256) double scratch[kScratchRows * 6];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static double *g_scratch_ptr[kMaxDevices] = {};
+
+// The address of `scratch` on device dev (which must be current).
+static lbt1_status scratch_on(int dev, double **out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(LBT1_EDEVICE, "device %d: at most %d devices", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!p) return fail(LBT1_EDEVICE, "hipGetSymbolAddress(scratch) returned no address");
+    g_scratch_ptr[dev] = (double *)p;
   }
-  a.flags = g->haswall ? g->flags : nullptr;
-  a.nx = g->nx;
-  a.ny = g->ny;
-  a.pitch = g->L.pitch;
-  a.rs = g->L.rs;
-  a.sc_d = g->sc[0];
-  a.sc_j = g->sc[1];
-  a.what = what;
-  a.partials = g->partials;
-  const long n = (long)g->nx * g->ny;
-  const int blocks = (int)std::min<long>(g->L.nparts, std::max<long>(1, (n + 1023) / 1024));
-  void *args[] = {&a};
-  hipError_t e = hipLaunchKernel(reduce_partial_kernel(g->prec), dim3(blocks), dim3(256), args, 0, s);
-  if (e != hipSuccess) return hip_fail(e, "reduce launch");
-  const double *parts = g->partials;
-  int np = blocks;
-  double *out = g->red_out;
-  void *args2[] = {&parts, &np, &out};
-  e = hipLaunchKernel(reduce_final_kernel(), dim3(1), dim3(64), args2, 0, s);
-  if (e != hipSuccess) return hip_fail(e, "reduce launch");
+  *out = g_scratch_ptr[dev];
   return LBT1_OK;
 }
 
@@ -1141,6 +1176,24 @@ lbt1_status lbt1_reduce(lbt1_grid *g, uint32_t what, double *out) {
   if (what & LBT1_REDUCE_NONFINITE) out[4] = r[4];
   out[5] = r[5];
   return LBT1_OK;
+}
+
+lbt1_status lbt1_reduce_noalloc(lbt1_grid *g, uint32_t what, double *out) {
+  clear_error();
+  if (!g || !out) return fail(LBT1_EINVAL, "null argument");
+  if (what & ~15u) return fail(LBT1_EINVAL, "unknown reduce bits %u", what);
+  if (!g->geometry) return fail(LBT1_ESTATE, "no geometry set");
+  if ((what & LBT1_REDUCE_RESIDUAL) && !g->snap[0]) return fail(LBT1_EINVAL, "grid was created without LBT1_OPT_SNAPSHOT");
+  if (g->batch) return fail(LBT1_ESTATE, "grid is resident in a batch");
+  const int rows = reduce_blocks(g);
+  if (rows > kScratchRows)
+    return fail(LBT1_EINVAL, "reduction needs %d partial rows, the static scratch holds %d", rows, kScratchRows);
+  hipError_t e;
+  if ((e = hipSetDevice(g->device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
+  double *parts = nullptr;
+  lbt1_status st = scratch_on(g->device, &parts);
+  if (st) return st;
+  return enqueue_reduce_into(g, what, g->stream, parts, out, true);
 }
 
 lbt1_status lbt1_destroy_grid(lbt1_grid *g) {

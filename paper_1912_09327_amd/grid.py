@@ -118,6 +118,12 @@ class Grid:
         return dict(mass=out[0], mom_x=out[1], mom_y=out[2], residual=out[3],
                     nonfinite=out[4], fluid=int(out[5]))
 
+    def reduce_noalloc(self, out_ptr, what=C.REDUCE_ALL):
+        """lbt1_reduce_noalloc: the diagnostics into caller device memory at ``out_ptr``
+        (REDUCE_SLOTS doubles), enqueued on the grid's stream; nothing is allocated
+        and nothing synchronises."""
+        C.check(C.lib.lbt1_reduce_noalloc(self.handle, int(what), ctypes.c_void_p(int(out_ptr))))
+
     def sync(self):
         C.check(C.lib.lbt1_sync(self.handle))
 
