@@ -213,6 +213,19 @@ lbt1_status lbt1_reduce(lbt1_grid *g, uint32_t what, double *out);
  * caller. */
 lbt1_status lbt1_reduce_noalloc(lbt1_grid *g, uint32_t what, double *out);
 
+/* Exact checkpoint and resume (the state is the paper's fields, Algorithm 1).
+ * lbt1_read_moments returns rho = 1 + (rho - 1) in FP64, which rounds for FP64
+ * storage; these calls move the stored bits instead.  lbt1_save_state copies the
+ * current state in storage format -- the parity block, then the residual
+ * snapshot when the grid keeps one, lbt1_state_bytes(g) bytes -- into caller host
+ * memory (EINVAL if `bytes` is smaller).  lbt1_load_state puts such a block back
+ * into a grid of the same shape, precision and options whose geometry (flags) is
+ * set, in both parities (EINVAL if `bytes` differs); stepping then continues bit
+ * for bit as the saved grid would have.  Both synchronise the grid's stream. */
+size_t lbt1_state_bytes(lbt1_grid *g);
+lbt1_status lbt1_save_state(lbt1_grid *g, void *host, size_t bytes);
+lbt1_status lbt1_load_state(lbt1_grid *g, const void *host, size_t bytes);
+
 /* Wait until all work enqueued on the grid's stream has finished. */
 lbt1_status lbt1_sync(lbt1_grid *g);
 

@@ -86,6 +86,9 @@ SIGNATURES = {
     "lbt1_read_populations": (ctypes.c_int, [_vp, _dp]),
     "lbt1_reduce": (ctypes.c_int, [_vp, ctypes.c_uint32, _dp]),
     "lbt1_reduce_noalloc": (ctypes.c_int, [_vp, ctypes.c_uint32, _vp]),
+    "lbt1_state_bytes": (ctypes.c_size_t, [_vp]),
+    "lbt1_save_state": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t]),
+    "lbt1_load_state": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t]),
     "lbt1_sync": (ctypes.c_int, [_vp]),
     "lbt1_destroy_grid": (ctypes.c_int, [_vp]),
     "lbt1_last_error": (ctypes.c_char_p, []),

@@ -1196,6 +1196,57 @@ lbt1_status lbt1_reduce_noalloc(lbt1_grid *g, uint32_t what, double *out) {
   return enqueue_reduce_into(g, what, g->stream, parts, out, true);
 }
 
+// Bytes of an exact checkpoint: the parity block in storage format, and the
+// residual snapshot when the grid keeps one.
+static size_t snapshot_bytes(const lbt1_grid *g) {
+  if (!g->snap[0]) return 0;
+  return g->pop ? 3 * (g->L.snap_field_off[1] - g->L.snap_field_off[0]) : g->L.state;
+}
+
+size_t lbt1_state_bytes(lbt1_grid *g) {
+  if (!g) return 0;
+  return g->L.state + snapshot_bytes(g);
+}
+
+lbt1_status lbt1_save_state(lbt1_grid *g, void *host, size_t bytes) {
+  clear_error();
+  if (!g || !host) return fail(LBT1_EINVAL, "null argument");
+  if (!g->geometry) return fail(LBT1_ESTATE, "no geometry set");
+  if (g->batch) return fail(LBT1_ESTATE, "grid is resident in a batch");
+  if (bytes < lbt1_state_bytes(g)) return fail(LBT1_EINVAL, "buffer has %zu bytes, the state %zu", bytes, lbt1_state_bytes(g));
+  hipError_t e;
+  if ((e = hipSetDevice(g->device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
+  if ((e = hipStreamSynchronize(g->stream)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  char *h = (char *)host;
+  if ((e = hipMemcpy(h, g->base + (size_t)g->parity * g->L.state, g->L.state, hipMemcpyDeviceToHost)) != hipSuccess)
+    return hip_fail(e, "hipMemcpy D2H");
+  if (snapshot_bytes(g) &&
+      (e = hipMemcpy(h + g->L.state, g->base + g->L.snap_off, snapshot_bytes(g), hipMemcpyDeviceToHost)) != hipSuccess)
+    return hip_fail(e, "hipMemcpy D2H");
+  return LBT1_OK;
+}
+
+lbt1_status lbt1_load_state(lbt1_grid *g, const void *host, size_t bytes) {
+  clear_error();
+  if (!g || !host) return fail(LBT1_EINVAL, "null argument");
+  if (!g->geometry) return fail(LBT1_ESTATE, "set the geometry (flags) before loading a state");
+  if (g->batch) return fail(LBT1_ESTATE, "grid is resident in a batch");
+  if (bytes != lbt1_state_bytes(g)) return fail(LBT1_EINVAL, "state has %zu bytes, this grid takes %zu", bytes, lbt1_state_bytes(g));
+  hipError_t e;
+  if ((e = hipSetDevice(g->device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
+  if ((e = hipStreamSynchronize(g->stream)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  const char *h = (const char *)host;
+  // both parities: non-FLUID nodes are read from either
+  for (int p = 0; p < 2; ++p)
+    if ((e = hipMemcpy(g->base + (size_t)p * g->L.state, h, g->L.state, hipMemcpyHostToDevice)) != hipSuccess)
+      return hip_fail(e, "hipMemcpy H2D");
+  if (snapshot_bytes(g) &&
+      (e = hipMemcpy(g->base + g->L.snap_off, h + g->L.state, snapshot_bytes(g), hipMemcpyHostToDevice)) != hipSuccess)
+    return hip_fail(e, "hipMemcpy H2D");
+  g->parity = 0;
+  return LBT1_OK;
+}
+
 lbt1_status lbt1_destroy_grid(lbt1_grid *g) {
   clear_error();
   if (!g) return LBT1_OK;

@@ -118,6 +118,19 @@ class Grid:
         return dict(mass=out[0], mom_x=out[1], mom_y=out[2], residual=out[3],
                     nonfinite=out[4], fluid=int(out[5]))
 
+    def save_state(self):
+        """The exact state in storage format (bytes): the checkpoint lbt1_load_state takes."""
+        n = int(C.lib.lbt1_state_bytes(self.handle))
+        buf = ctypes.create_string_buffer(n)
+        C.check(C.lib.lbt1_save_state(self.handle, buf, n))
+        return buf.raw
+
+    def load_state(self, state):
+        """Resume from save_state's bytes (same shape, precision and options; the
+        geometry must be set)."""
+        buf = ctypes.create_string_buffer(bytes(state), len(state))
+        C.check(C.lib.lbt1_load_state(self.handle, buf, len(state)))
+
     def reduce_noalloc(self, out_ptr, what=C.REDUCE_ALL):
         """lbt1_reduce_noalloc: the diagnostics into caller device memory at ``out_ptr``
         (REDUCE_SLOTS doubles), enqueued on the grid's stream; nothing is allocated
