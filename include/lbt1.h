@@ -346,8 +346,9 @@ lbt1_status lbt1_grid3d_destroy(lbt1_grid3d *g);
 
 /* ---------------------------------------------------------------- batches */
 
-/* A batch steps every resident grid together: one launch per time step covers
- * the strips of all grids, and bursts of steps run as a HIP graph.
+/* A batch steps every resident grid together: one launch per time step (or per
+ * two steps, see lbt1_batch_shape) covers the strips of all grids of a work
+ * class, and bursts of steps run as a HIP graph.
  *   hbm_budget_bytes: admission limit on the sum of lbt1_grid_bytes of resident grids
  *   max_slots:        admission limit on the number of resident grids (1..65536)
  *   stream:           hipStream_t for the batch's work, NULL for a library stream
@@ -386,6 +387,45 @@ enum {
 /* State of a slot: reason (LBT1_SLOT_*), steps taken since admission, last residual. */
 lbt1_status lbt1_batch_slot_info(lbt1_batch *b, int32_t slot, int32_t *state, int64_t *steps,
                                  double *residual);
+
+/* Tile shape of a batch.  Every resident grid runs in one of five work classes:
+ * one step per launch at 1, 2 or 4 columns per lane (classes 0, 1, 2; strips of
+ * 62 chunks of that many columns; a grid takes the widest class that fits it),
+ * two steps per launch at 2 columns per lane (class 3, the fused class: the state
+ * crosses memory once per two steps, as lbt1_kernel_config.fuse = 2 does for one
+ * grid), or resident in LDS for a whole burst (class 4: one workgroup per grid
+ * copies the grid into LDS, takes all of its steps of the burst there and writes
+ * it back; grids whose two copies fit 64 KiB of LDS, about 64 x 64 nodes in 16-bit
+ * storage, 45 x 45 in FP32; not FP64).  Results are bit for bit the same in every class. */
+enum {
+  LBT1_BATCH_FUSE_NONE = 0,   /* every grid one step per launch */
+  LBT1_BATCH_FUSE_ALL = 1,    /* every grid whose rows 2 columns per lane fit in the fused class */
+  LBT1_BATCH_FUSE_NARROW = 2  /* the fused class for grids narrower than the 4-column class */
+};
+typedef struct {
+  int32_t fuse;     /* LBT1_BATCH_FUSE_* */
+  int32_t lds;      /* 1: grids that fit run resident in LDS (class 4); 0: they do not */
+  int32_t rows[5];  /* strip height of classes 0..4: 6 or 14 for classes 0-2 and 4; 2, 6,
+                       14 or 30 (not 30 in FP64) for class 3; 0 = the library's heuristic
+                       (14 rows where a class has eight or more strips per CU, else 6) */
+} lbt1_batch_shape;
+
+/* Take a tile shape for the following bursts.  EINVAL for a shape that is not built. */
+lbt1_status lbt1_batch_set_shape(lbt1_batch *b, const lbt1_batch_shape *shape);
+
+/* The fuse mode in force and the strip heights the resident grids run with now. */
+lbt1_status lbt1_batch_get_shape(lbt1_batch *b, lbt1_batch_shape *shape);
+
+/* Time tile shapes on the resident, running grids and keep the fastest: each fuse
+ * and LDS mode that changes some grid's class, with the strip height of each class chosen
+ * in turn (coordinate descent), every candidate timed as bursts of burst_steps
+ * steps as lbt1_batch_run runs them (the best of `reps` after one untimed burst).
+ * The grids' device memory is saved to scratch first and restored afterwards
+ * (ENOMEM when the scratch does not fit), and no step counts, parities or slot
+ * states change.  *best (optional) receives the shape, *ms_per_burst (optional)
+ * its time.  ESTATE when no grid is running.  Synchronises. */
+lbt1_status lbt1_batch_autotune(lbt1_batch *b, int32_t burst_steps, int32_t reps, lbt1_batch_shape *best,
+                                double *ms_per_burst);
 
 /* Remove the grid in `slot` from the batch (it stays valid and owned by the caller). */
 lbt1_status lbt1_batch_evict(lbt1_batch *b, int32_t slot);

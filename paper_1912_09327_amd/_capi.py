@@ -61,6 +61,13 @@ class KernelConfig(ctypes.Structure):
         return dict(kernel=self.kernel, vec=self.vec, rows=self.rows, waves=self.waves, fuse=self.fuse)
 
 
+class BatchShape(ctypes.Structure):
+    _fields_ = [("fuse", ctypes.c_int32), ("lds", ctypes.c_int32), ("rows", ctypes.c_int32 * 5)]
+
+    def as_dict(self):
+        return dict(fuse=self.fuse, lds=self.lds, rows=list(self.rows))
+
+
 class Grid3DDesc(ctypes.Structure):
     _fields_ = [
         ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32), ("q", ctypes.c_int32),
@@ -100,6 +107,9 @@ SIGNATURES = {
     "lbt1_batch_run": (ctypes.c_int, [_vp, _i32]),
     "lbt1_batch_poll": (ctypes.c_int, [_vp, ctypes.POINTER(_i32), _i32, ctypes.POINTER(_i32)]),
     "lbt1_batch_slot_info": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(_i32), ctypes.POINTER(ctypes.c_int64), _dp]),
+    "lbt1_batch_set_shape": (ctypes.c_int, [_vp, ctypes.POINTER(BatchShape)]),
+    "lbt1_batch_get_shape": (ctypes.c_int, [_vp, ctypes.POINTER(BatchShape)]),
+    "lbt1_batch_autotune": (ctypes.c_int, [_vp, _i32, _i32, ctypes.POINTER(BatchShape), _dp]),
     "lbt1_batch_evict": (ctypes.c_int, [_vp, _i32]),
     "lbt1_batch_destroy": (ctypes.c_int, [_vp]),
     "lbt1_probe_bandwidth": (ctypes.c_int, [_i32, ctypes.c_size_t, _i32, _i32, _dp]),

@@ -33,6 +33,27 @@ class Batch:
     def run(self, burst_steps):
         C.check(C.lib.lbt1_batch_run(self.handle, int(burst_steps)))
 
+    def set_shape(self, fuse=0, rows=(0, 0, 0, 0, 0), lds=0):
+        """Tile shape: fuse mode (0 none, 1 all, 2 narrow grids), LDS residency of small
+        grids (0 / 1) and the strip height of the five work classes (0 = heuristic)."""
+        rows = list(rows) + [0] * (5 - len(rows))
+        sh = C.BatchShape(int(fuse), int(lds), (ctypes.c_int32 * 5)(*[int(r) for r in rows]))
+        C.check(C.lib.lbt1_batch_set_shape(self.handle, ctypes.byref(sh)))
+
+    def shape(self):
+        sh = C.BatchShape()
+        C.check(C.lib.lbt1_batch_get_shape(self.handle, ctypes.byref(sh)))
+        return sh.as_dict()
+
+    def autotune(self, burst_steps=20, reps=3):
+        """Time tile shapes on the running grids (state restored) and keep the fastest;
+        returns (shape, ms per burst)."""
+        sh = C.BatchShape()
+        ms = ctypes.c_double()
+        C.check(C.lib.lbt1_batch_autotune(self.handle, int(burst_steps), int(reps), ctypes.byref(sh),
+                                          ctypes.byref(ms)))
+        return sh.as_dict(), ms.value
+
     def poll(self):
         cap = max(1, len(self.grids))
         buf = (ctypes.c_int32 * cap)()

@@ -55,7 +55,9 @@ struct BgkReduceArgs {
 
 // Descriptor of one resident grid (device copy refreshed by the host before
 // every burst).  parity0 is the grid's parity at the start of the burst;
-// the grid takes steps_left (<= burst length) steps in this burst.
+// the grid takes steps_left (<= burst length) steps in this burst, in `flips`
+// launches (each launch reads one parity and writes the other: one launch per
+// step, one per two steps in the fused class, one per burst in the LDS class).
 struct BatchGrid {
   void *plane[2][3];
   const uint8_t *flags;
@@ -64,10 +66,21 @@ struct BatchGrid {
   int wall;
   int parity0;
   int steps_left;
+  int flips;
   int strips_x;  // strips per row band (columns of 64 * vec)
   double fx, fy, sc_d, sc_j, is_d, is_j;
   void *trash;  // see StepArgs::trash
 };
+
+// Bytes of LDS a grid takes in the batch's LDS-resident class: two copies of its
+// three fields on rows of ceil(nx / vec) * vec values (the last chunk padded), one
+// flag byte per such node, and the 3 KiB trash area of redirected stores.
+__host__ __device__ inline long lds_grid_bytes(int nx, int ny, int vec, int value_bytes) {
+  const long pitch = (long)((nx + vec - 1) / vec) * vec;
+  const long state = (long)ny * 3 * pitch * value_bytes;
+  const long flags = ((long)ny * pitch + 15) / 16 * 16;
+  return 2 * state + flags + 3 * kTrashRegion;
+}
 
 struct BatchStepArgs {
   const BatchGrid *grids;

@@ -25,6 +25,8 @@ const void *reduce_final_out_kernel();  // final pass writing the user-facing sl
 const void *bgk_reduce_partial_kernel(int prec);
 const void *bgk_psi_kernel(int prec);
 const void *batch_step_kernel(int prec, int vec_class, int rows);
+const void *batch_fused_kernel(int prec, int rows);  // two steps per launch, two columns per lane
+const void *batch_lds_kernel(int prec, int rows);    // grids resident in LDS for a burst
 const void *batch_reduce_kernel(int prec);
 const void *batch_reduce_final_kernel();
 

@@ -1,6 +1,7 @@
 // Instantiation of the step and reduction kernels and the table the runtime
 // selects from.
 #include "lbt1_internal.hpp"
+#include "lbt1_batch_kernels.hpp"
 #include "lbt1_bgk.hpp"
 #include "lbt1_fused.hpp"
 #include "lbt1_fused_wall.hpp"
@@ -200,6 +201,35 @@ const void *batch_step_kernel(int prec, int vec_class, int rows) {
   if (prec < 0 || prec > 3 || vec_class < 0 || vec_class > 3) return nullptr;
   if (rows == 14) return tall[prec][vec_class];
   if (rows == 6) return shrt[prec][vec_class];
+  return nullptr;
+}
+
+// Two steps per launch, two columns per lane, strips of 2, 6, 14 or 30 rows (FP64
+// at 30 rows would spill, as the single-grid kernel of that shape does).
+const void *batch_fused_kernel(int prec, int rows) {
+#define BATCH_FUSED(P) \
+  if (rows == 2) return (const void *)&k_step_batch_fused<P, 2>; \
+  if (rows == 6) return (const void *)&k_step_batch_fused<P, 6>; \
+  if (rows == 14) return (const void *)&k_step_batch_fused<P, 14>;
+  switch (prec) {
+    case P_F64: { BATCH_FUSED(P_F64) break; }
+    case P_F32: { BATCH_FUSED(P_F32) if (rows == 30) return (const void *)&k_step_batch_fused<P_F32, 30>; break; }
+    case P_F16S: { BATCH_FUSED(P_F16S) if (rows == 30) return (const void *)&k_step_batch_fused<P_F16S, 30>; break; }
+    case P_BF16S: { BATCH_FUSED(P_BF16S) if (rows == 30) return (const void *)&k_step_batch_fused<P_BF16S, 30>; break; }
+  }
+#undef BATCH_FUSED
+  return nullptr;
+}
+
+// Grids resident in LDS for a burst: two columns per lane, strips of 6 or 14 rows
+// (not FP64: its kernel would spill scalar registers, and only grids of about 32 x 32
+// nodes would fit).
+const void *batch_lds_kernel(int prec, int rows) {
+  switch (prec) {
+    case P_F32: return rows == 6 ? (const void *)&k_step_batch_lds<P_F32, 2, 6> : rows == 14 ? (const void *)&k_step_batch_lds<P_F32, 2, 14> : nullptr;
+    case P_F16S: return rows == 6 ? (const void *)&k_step_batch_lds<P_F16S, 2, 6> : rows == 14 ? (const void *)&k_step_batch_lds<P_F16S, 2, 14> : nullptr;
+    case P_BF16S: return rows == 6 ? (const void *)&k_step_batch_lds<P_BF16S, 2, 6> : rows == 14 ? (const void *)&k_step_batch_lds<P_BF16S, 2, 14> : nullptr;
+  }
   return nullptr;
 }
 

@@ -447,9 +447,55 @@ namespace lbt1 {
 // ================================================================ batched step
 
 
+// Step arguments of a resident grid reading parity p.
+__device__ __forceinline__ StepArgs batch_step_args(const BatchGrid &g, const int p) {
+  StepArgs a;
+  for (int q = 0; q < 3; ++q) {
+    a.src[q] = g.plane[p][q];
+    a.dst[q] = g.plane[1 - p][q];
+  }
+  a.flags = g.flags;
+  a.nx = g.nx;
+  a.ny = g.ny;
+  a.pitch = g.pitch;
+  a.rs = g.rs;
+  a.periodic = g.periodic;
+  a.fx = g.fx;
+  a.fy = g.fy;
+  a.sc_d = g.sc_d;
+  a.sc_j = g.sc_j;
+  a.is_d = g.is_d;
+  a.is_j = g.is_j;
+  a.trash = g.trash;
+  a.sc_G = 0.0;
+  a.sc_rho0 = 1.0;
+  return a;
+}
+
+// True when every node the strip at (chunk0, y0) reads -- its NY rows, HALO rows
+// above and below, the 64 chunks of its lanes -- lies inside the grid and is a
+// FLUID node: no wall or fixed node, no row or column across an axis.  Such a strip
+// takes the wall-free body, which gives the same bits (the wall rule only ever
+// replaces arrivals from SOLID sources, and the sums run in the same order).
+// Wave-uniform: the flags of the footprint are OR-ed per lane, then voted.
+template <int VEC>
+__device__ __forceinline__ bool strip_interior(const StepArgs &a, const int chunk0, const int y0, const int NY,
+                                               const int HALO) {
+  if (chunk0 < 1 || (chunk0 + 63) * VEC > a.nx || y0 < HALO || y0 + NY + HALO > a.ny) return false;
+  const int lane = threadIdx.x & 63;
+  const uint8_t *f = a.flags + (long)(y0 - HALO) * a.pitch + (chunk0 - 1 + lane) * VEC;
+  uint32_t any = 0;
+  for (int i = 0; i < NY + 2 * HALO; ++i) {
+    const Pack<uint8_t, VEC> p = *reinterpret_cast<const Pack<uint8_t, VEC> *>(f + (long)i * a.pitch);
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) any |= p.v[v];
+  }
+  return __ballot(any != 0) == 0;
+}
+
 // One wavefront per work item, grid-stride over all items of every grid with
-// columns per lane VEC.  Always takes the wall-aware path: on a grid with no
-// walls it gives the same bits as the wall-free kernels.
+// columns per lane VEC.  Strips whose footprint holds walls, fixed nodes or an
+// edge of the grid take the wall-aware body, the others the wall-free one.
 template <int P, int VEC, int NY>
 __global__ void __launch_bounds__(256) k_step_batch(BatchStepArgs b) {
   const int lane = threadIdx.x & 63;
@@ -459,31 +505,18 @@ __global__ void __launch_bounds__(256) k_step_batch(BatchStepArgs b) {
     const int2 item = b.items[it];
     const BatchGrid &g = b.grids[item.x];
     if (b.step >= g.steps_left) continue;
-    const int p = (g.parity0 + b.step) & 1;
-    StepArgs a;
-    for (int q = 0; q < 3; ++q) {
-      a.src[q] = g.plane[p][q];
-      a.dst[q] = g.plane[1 - p][q];
-    }
-    a.flags = g.flags;
-    a.nx = g.nx;
-    a.ny = g.ny;
-    a.pitch = g.pitch;
-    a.rs = g.rs;
-    a.periodic = g.periodic;
-    a.fx = g.fx;
-    a.fy = g.fy;
-    a.sc_d = g.sc_d;
-    a.sc_j = g.sc_j;
-    a.is_d = g.is_d;
-    a.is_j = g.is_j;
-    a.trash = g.trash;
+    const StepArgs a = batch_step_args(g, (g.parity0 + b.step) & 1);
     const int sy = item.y / g.strips_x;   // along each row band, as in k_step_strip
     const int sx = item.y - sy * g.strips_x;
     // unit storage scales (the default; a wave-uniform test): the body without
     // the scaling multiplications, which are exact no-ops then
     const bool unit = !Traits<P>::kScaled || (g.sc_d == 1.0 && g.sc_j == 1.0 && g.is_d == 1.0 && g.is_j == 1.0);
-    if (g.wall == WALL_PAPER) {
+    if (strip_interior<VEC>(a, sx * 62, sy * NY, NY, 1)) {
+      if (unit)
+        strip_body<P, false, 0, VEC, NY, true>(a, sx * 62, sy * NY, lane);
+      else
+        strip_body<P, false, 0, VEC, NY, false>(a, sx * 62, sy * NY, lane);
+    } else if (g.wall == WALL_PAPER) {
       if (!Traits<P>::kScaled || unit)
         strip_body<P, true, WALL_PAPER, VEC, NY, true>(a, sx * 62, sy * NY, lane);
       else
@@ -509,7 +542,7 @@ __global__ void __launch_bounds__(256) k_reduce_batch(BatchReduceArgs b) {
     const int slot = item.x;
     const BatchGrid &g = b.grids[slot];
     if (g.steps_left == 0) continue;  // not stepped in this burst (uniform in the block)
-    const int p = (g.parity0 + g.steps_left) & 1;
+    const int p = (g.parity0 + g.flips) & 1;
     const S *c0 = static_cast<const S *>(g.plane[p][0]);
     const S *c1 = static_cast<const S *>(g.plane[p][1]);
     const S *c2 = static_cast<const S *>(g.plane[p][2]);

@@ -70,6 +70,89 @@ def test_batch_alone_vs_mix_bitwise(prec):
     b.close()
 
 
+def _run_mix_and_compare(prec, shape=None, burst=40, tune=False):
+    """Run SPECS with BUDGETS in one batch (the given tile shape, or the autotuner's
+    choice after two bursts) and compare every grid with the gather kernel alone."""
+    from paper_1912_09327_amd.batch import Batch
+    from paper_1912_09327_amd.grid import Grid
+    b = Batch(1 << 30, 16)
+    if shape is not None:
+        b.set_shape(*shape)
+    grids = []
+    for spec, budget in zip(SPECS, BUDGETS):
+        g, geo = _grid(spec, prec)
+        slot = b.admit(g, budget, -1.0)
+        assert slot is not None
+        grids.append((g, geo, budget, slot))
+    got_shape = None
+    for k in range(40):
+        if tune and k == 2:
+            got_shape, ms = b.autotune(burst_steps=20, reps=2)
+            assert ms > 0
+        b.run(burst)
+        if len(b.poll()) == len(grids):
+            break
+    assert len(b.poll()) == len(grids)
+    for g, geo, budget, slot in grids:
+        state, steps, _ = b.slot_info(slot)
+        assert steps == budget
+        b.evict(slot)
+        mix = g.read_moments()
+        g.close()
+        flags, rho, jx, jy, per, F = geo
+        h = Grid(flags.shape[1], flags.shape[0], prec=prec, periodic=per, force=F)
+        h.set_geometry(flags, rho, jx, jy)
+        h.set_kernel("gather")
+        h.step(budget)
+        alone = h.read_moments()
+        h.close()
+        for a, c in zip(mix, alone):
+            assert np.array_equal(a, c), (shape, got_shape, geo[0].shape, budget)
+    b.close()
+    return got_shape
+
+
+# tile shapes: fuse mode, strip heights of the five classes (one step at 1, 2, 4
+# columns per lane; two steps at 2; resident in LDS) and LDS residency of small grids
+SHAPES = [(1, (6, 6, 6, 2, 0), 0), (1, (14, 14, 14, 6, 0), 0), (2, (6, 14, 6, 14, 0), 0), (1, (0, 0, 0, 30, 0), 0),
+          (0, (14, 6, 14, 0, 0), 0), (0, (0, 0, 0, 0, 6), 1), (1, (6, 6, 6, 14, 14), 1)]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16s", "bf16s"])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_batch_tile_shapes_alone_vs_mix_bitwise(prec, shape):
+    """Every tile shape, odd budgets, bursts of an odd number of steps (the fused class
+    then ends a burst with a single step): the bits of each grid alone."""
+    if prec == "f64" and shape[1][3] == 30:
+        pytest.skip("two-step FP64 strips of 30 rows are not built")
+    _run_mix_and_compare(prec, shape, burst=33)
+
+
+@pytest.mark.parametrize("prec", ["f32", "f16s"])
+def test_batch_autotune_keeps_state_and_bits(prec):
+    """The autotuner times shapes on the resident grids' memory and restores it: after
+    it the batch still ends every grid where the grid alone ends."""
+    shape = _run_mix_and_compare(prec, None, burst=40, tune=True)
+    assert shape["fuse"] in (0, 1, 2) and shape["lds"] in (0, 1) and len(shape["rows"]) == 5
+
+
+def test_batch_shape_refusals():
+    from paper_1912_09327_amd import _capi as C
+    from paper_1912_09327_amd.batch import Batch
+    b = Batch(1 << 28, 4)
+    try:
+        for bad in ((3, (0, 0, 0, 0)), (0, (7, 0, 0, 0)), (1, (0, 0, 0, 22)), (0, (0, 0, 0, 0, 22)),
+                    (0, (0, 0, 0, 0), 2)):
+            with pytest.raises(C.Lbt1Error) as e:
+                b.set_shape(*bad)
+            assert e.value.status == C.EINVAL
+        with pytest.raises(C.Lbt1Error) as e:
+            b.autotune()
+        assert e.value.status == C.ESTATE          # nothing resident
+    finally:
+        b.close()
+
+
 def test_batch_f64_matches_oracle():
     from paper_1912_09327_amd.batch import Batch
     b = Batch(1 << 30, 4)
