@@ -78,6 +78,13 @@ def parse():
     p.add_argument("--requests", type=int, default=200)
     p.add_argument("--budget-mib", type=int, default=1024, help="serve: HBM budget of the server")
     p.add_argument("--load", type=float, default=0.7)
+    p.add_argument("--no-batched", action="store_true", help="periodic: skip the batched-cavities sub-record")
+    p.add_argument("--no-serve", action="store_true", help="periodic: skip the serving sub-record")
+    p.add_argument("--batched-steps", type=int, default=2000,
+                   help="periodic: steps of every cavity in the batched sub-record")
+    p.add_argument("--serve-requests", type=int, default=100, help="periodic: requests of the serving sub-record")
+    p.add_argument("--batch-shape", default=None,
+                   help="cavities: fix the batch tile shape, fuse:rows0:rows1:rows2:rows3 (no autotuning)")
     return p.parse_args()
 
 
@@ -99,35 +106,72 @@ def make_grid(n, storage, state, tune=True, kernel=None, planar=False):
     return g
 
 
+def reduction_block(per_launch):
+    """Steps between two FP64 reductions: 100, or the whole number of launches of
+    `per_launch` steps closest below it (99 for three-step launches)."""
+    return max(per_launch, 100 // per_launch * per_launch)
+
+
+def run_schedule(steps, warmup, per_launch):
+    """The segments of a run of `warmup` untimed then `steps` timed steps: a list of
+    (timed, steps of whole launches, remainder steps, reduce after).  The reduction
+    runs every reduction_block() steps counted from the start of the run, warmup
+    included, whatever the timed length; a segment ends at each reduction and at the
+    end of the warmup, and its steps are split into whole launches and a remainder
+    (shorter launches), so the kernel time per step comes from whole launches only."""
+    block = reduction_block(per_launch)
+    out = []
+    t = 0
+    for timed, n in ((False, warmup), (True, steps)):
+        left = n
+        while left > 0:
+            k = min(left, block - t % block)
+            whole = k - k % per_launch
+            t += k
+            left -= k
+            out.append((timed, whole, k - whole, t % block == 0))
+    return out
+
+
 def timed_run(g, steps, warmup, torch, per_launch=1):
-    """Warm up, then time exactly `steps` steps: a reduction after every block of about
-    100 steps, HIP events around every block of step launches on the grid's stream.
-    A block is a whole number of launches of `per_launch` steps (99 steps for three),
-    so only the last block can end in a shorter launch; the per-step kernel time
-    comes from the whole-launch blocks."""
+    """Warm up, then time exactly `steps` steps (the schedule of run_schedule), with
+    HIP events on the grid's stream around the whole launches of every timed segment.
+    Returns (wall seconds, kernel ms per step over whole launches, schedule info)."""
     s = g.stream
-    g.step(warmup)
-    g.reduce()
-    torch.cuda.synchronize()
+    sched = run_schedule(steps, warmup, per_launch)
     ev = []
-    block = max(per_launch, 100 // per_launch * per_launch)
-    t0 = time.perf_counter()
-    done = 0
-    while done < steps:
-        k = min(block, steps - done)
-        a = torch.cuda.Event(enable_timing=True)
-        b = torch.cuda.Event(enable_timing=True)
-        a.record(s)
-        g.step(k)
-        b.record(s)
-        ev.append((a, b, k))
-        done += k
-        g.reduce()                       # FP64 mass / residual / non-finite, synchronises
+    reductions = 0
+    t0 = None
+    for timed, whole, rem, red in sched:
+        if timed and t0 is None:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+        if timed and whole:
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(s)
+            g.step(whole)
+            b.record(s)
+            ev.append((a, b, whole))
+        elif whole:
+            g.step(whole)
+        if rem:
+            g.step(rem)
+        if red:
+            g.reduce()                       # FP64 mass / residual / non-finite, synchronises
+            reductions += timed
+    if t0 is None:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    whole = [(a, b, k) for a, b, k in ev if k % per_launch == 0] or ev
-    kern_ms = sum(a.elapsed_time(b) for a, b, _ in whole)
-    return wall, kern_ms / sum(k for _, _, k in whole)
+    if ev:
+        kern_ms = sum(a.elapsed_time(b) for a, b, _ in ev) / sum(k for _, _, k in ev)
+    else:
+        kern_ms = wall * 1e3 / max(steps, 1)
+    info = dict(reduction_every=reduction_block(per_launch), reductions_timed=reductions,
+                steps_in_whole_launches=sum(k for _, _, k in ev))
+    return wall, kern_ms, info
 
 
 def copy_ceiling(nbytes=2 << 30):
@@ -188,6 +232,19 @@ def measured_traffic(storage, kernel_name, kernel_ms):
                 GBps=rec["traffic_bytes"] / (kernel_ms * 1e-3) / 1e9)
 
 
+def host_cpu():
+    """CPU model, logical cores of the host and cores this process may use."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return dict(model=model, host_logical_cores=os.cpu_count(), usable_cores=len(os.sched_getaffinity(0)))
+
+
 def cpu_baseline(state, budget_s):
     """The FP64 oracle on a 2048 x 2048 window of the same random field, OpenMP over rows."""
     import oracle
@@ -203,7 +260,7 @@ def cpu_baseline(state, budget_s):
     t0 = time.perf_counter()
     oracle.run(*sub, n, None, 3)
     dt = time.perf_counter() - t0
-    out = dict(value=round(m * m * n / dt / 1e6, 2), unit="MLUPS", cores=threads, kind="oracle",
+    out = dict(value=round(m * m * n / dt / 1e6, 2), unit="MLUPS", cores=threads, kind="oracle", host=host_cpu(),
                sample=f"{m}x{m} periodic window of the same seed-0 random field, {n} steps, "
                       f"FP64, {threads} OpenMP threads, {dt:.1f} s")
     # the same oracle on one thread, a 512 x 512 window for about a third of the budget
@@ -283,13 +340,13 @@ def run_periodic(args, torch):
         cfg, kname = g.kernel()
         log(f"[bench] {storage}: kernel {kname} {cfg}")
         K = max(1, cfg.get("fuse", 1)) if cfg.get("kernel") == 2 else 1   # steps per launch
-        wall, kms = timed_run(g, args.steps, args.warmup, torch, K)
+        wall, kms, sched = timed_run(g, args.steps, args.warmup, torch, K)
         c = VALUE_BYTES[storage]
         launch_ms = kms * K
         achieved = 2 * 3 * c * lups / (launch_ms * 1e-3) / 1e9
         results[storage] = dict(mlups=lups * args.steps / wall / 1e6, ms_per_step=wall * 1e3 / args.steps,
                                 kernel_ms=launch_ms, steps_per_launch=K, achieved=achieved, kernel=kname,
-                                config=cfg)
+                                config=cfg, schedule=sched)
         log(f"[bench] {storage}: {results[storage]['mlups']:.0f} MLUPS, launch {launch_ms:.4f} ms "
             f"({K} step(s)), "
             f"{achieved:.0f} GB/s")
@@ -313,7 +370,9 @@ def run_periodic(args, torch):
         "config": {"workload": f"periodic {n}x{n} random field (rho = 1 + 1e-3 N(0,1), "
                                f"u = 0.01 N(0,1), seed 0), {args.storage} moment storage",
                    "nx": n, "ny": n, "storage": args.storage, "fluid_nodes": int(lups),
-                   "reduction_every": max(head["steps_per_launch"], 100 // head["steps_per_launch"] * head["steps_per_launch"]),
+                   "reduction_every": head["schedule"]["reduction_every"],
+                   "reductions_timed": head["schedule"]["reductions_timed"],
+                   "steps_in_whole_launches": head["schedule"]["steps_in_whole_launches"],
                    "kernel": head["kernel"], "kernel_config": head["config"]},
         "roofline": {"bound": "hbm", "achieved": round(head["achieved"], 1), "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": round(head["achieved"] / HBM_PEAK_GBPS, 4), "traffic": None,
@@ -364,6 +423,30 @@ def run_periodic(args, torch):
     if not args.no_cpu:
         log("[bench] CPU oracle baseline")
         line["cpu_baseline"] = cpu_baseline(state, args.cpu_seconds)
+    del state
+    torch.cuda.empty_cache()
+    # the metric's second half: the batched and served forms against the plain
+    # one-grid-at-a-time form, bounded samples of the uneven-cavity and request workloads
+    from paper_1912_09327_amd import workloads as W
+    if not args.no_batched:
+        log(f"[bench] batched sub-record: {args.cavities} cavities x {args.batched_steps} steps")
+        r = W.run_cavities(args.cavities, args.batched_steps, -1.0, torch, log)
+        r["workload"] = (f"{r['cavities']} lid-driven cavities, side log-uniform [32, 512], lid U[0.01, 0.1], "
+                         f"seed 4, FP16 shifted storage, FP32 arithmetic, {args.batched_steps} steps each, "
+                         "residual check every 100 steps")
+        line["batched"] = r
+        torch.cuda.empty_cache()
+    if not args.no_serve:
+        budget = int(args.budget_mib) << 20
+        log(f"[bench] serve sub-record: {args.serve_requests} requests at load {args.load}")
+        cap, rate, reqs, served, s_srv, s_pl = W.run_serve(args.serve_requests, args.load, budget, torch, log)
+        line["serve"] = dict(
+            workload=f"{len(reqs)} Poisson requests (seed 5) at {rate:.3f}/s, load {args.load} of the measured "
+                     f"capacity {cap:.3f}/s, half lid-driven cavities half porous channels, side 32..2048, "
+                     f"budgets 1e3..1e5 steps, FP16 storage, {budget >> 20} MiB HBM budget, 64 slots",
+            capacity_req_per_s=round(cap, 3), rate_per_s=round(rate, 3), server=s_srv, plain=s_pl,
+            p99_speedup=round(s_pl["p99_s"] / s_srv["p99_s"], 2) if s_srv["p99_s"] else None,
+            mlups_ratio=round(s_srv["mlups"] / s_pl["mlups"], 3) if s_pl["mlups"] else None)
     return line
 
 
@@ -425,7 +508,7 @@ def run_cavity(args, torch):
         t0 = time.perf_counter()
         oracle.run(rho, jx, jy, m, flags, per)
         dt = time.perf_counter() - t0
-        line["cpu_baseline"] = dict(value=round(fluid * m / dt / 1e6, 2), unit="MLUPS", cores=threads, kind="oracle",
+        line["cpu_baseline"] = dict(value=round(fluid * m / dt / 1e6, 2), unit="MLUPS", cores=threads, kind="oracle", host=host_cpu(),
                                     sample=f"the same {n}x{n} cavity, {m} steps, FP64, {threads} OpenMP threads, "
                                            f"{dt:.1f} s")
     return line
@@ -461,7 +544,7 @@ def run_compare(args, torch):
         cfg, kname = g.kernel()
         log(f"[compare] {name}: {kname}")
         K = cfg.get("fuse", 1) if cfg.get("kernel") == 2 else 1
-        wall, kms = timed_run(g, args.steps, args.warmup, torch, K)
+        wall, kms, _ = timed_run(g, args.steps, args.warmup, torch, K)
         per_node = (2 * 9 * c) if kw["populations"] else (2 * 3 * c)     # state bytes per node
         alg = per_node * lups                                          # read + write per launch
         rows[name] = dict(kernel=kname, mlups=round(lups * args.steps / wall / 1e6, 1),
@@ -579,7 +662,7 @@ def run_drop(args, torch):
             g.set_geometry(None, rho, z, z)
             if not kw:
                 g.autotune(steps=30, reps=3)
-            wall, kms = timed_run(g, steps, min(100, steps // 4), torch)
+            wall, kms, _ = timed_run(g, steps, min(100, steps // 4), torch)
             dd = g.reduce()
             opts = g.options & ~C.OPT_SNAPSHOT
             rec[name] = dict(kernel=g.kernel()[1], it_per_s=round(steps / wall, 1),

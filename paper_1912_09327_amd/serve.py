@@ -9,10 +9,15 @@ its step budget is used, and its slot and memory are handed to the next
 request at once.  Latency is finish time minus arrival time, queueing
 included.
 
+Admission is in arrival order, except that a request that does not fit the
+free HBM budget may be overtaken by later ones that do, at most
+``max_overtakes`` times; after that nothing behind it is admitted until it is
+(a reservation, so no request starves).
+
 The plain baseline serves the same requests one at a time in arrival order,
-each with one launch per step (``lbt1_step``) and the same residual checks at
-the same burst boundaries, so each result is bit-for-bit the one the server
-produces for it.
+each stepped alone with ``lbt1_step`` (the library's default kernel for the grid,
+graph bursts) and the same residual checks at the same burst boundaries, so each
+result is bit-for-bit the one the server produces for it.
 
 The scheduling logic talks to a ``Backend`` (``GpuBackend`` here); the tests
 drive it with a CPU stand-in.
@@ -184,11 +189,13 @@ class Server:
     """Continuous batching with admission by HBM budget and slot count."""
 
     def __init__(self, backend, hbm_budget_bytes, max_slots, burst=100, keep_results=False, clock=None,
-                 sleep=None, progress=None):
+                 sleep=None, progress=None, max_overtakes=16):
         self.b = backend
         self.budget = int(hbm_budget_bytes)
         self.max_slots = int(max_slots)
         self.burst = int(burst)
+        self.max_overtakes = int(max_overtakes)
+        self.overtaken = {}            # request id -> times a later request was admitted first
         self.keep = keep_results
         self.clock = clock or time.perf_counter
         self.sleep = sleep or time.sleep
@@ -212,13 +219,17 @@ class Server:
                 req = pending.popleft()
                 queue.append(req)
                 geo[req.id] = pool.submit(geometry, req)
-            # admit in arrival order while the head fits (no overtaking, so no starvation)
-            while queue and len(active) < self.max_slots:
-                req = queue[0]
+            # admit in arrival order; a request the free budget cannot hold yet may be
+            # overtaken by later ones that fit, at most max_overtakes times, after which
+            # nothing behind it is admitted before it (no starvation)
+            i = 0
+            blocked = []               # requests ahead of i that did not fit
+            while i < len(queue) and len(active) < self.max_slots:
+                req = queue[i]
                 nbytes = self.b.grid_bytes(req)
                 if nbytes > self.budget:
                     # can never fit: refused at once, the queue moves on
-                    queue.popleft()
+                    del queue[i]
                     geo.pop(req.id).cancel()
                     now = self.clock() - t0
                     done.append(Result(req.id, req.arrival, now, now, 0, "refused", float("nan"), 0.0))
@@ -226,13 +237,20 @@ class Server:
                         self.progress(len(done), now)
                     continue
                 if used + nbytes > self.budget:
-                    break
+                    if self.overtaken.get(req.id, 0) >= self.max_overtakes:
+                        break          # reserved: wait until it fits
+                    blocked.append(req)
+                    i += 1
+                    continue
                 handle = self.b.create(req, geo.pop(req.id).result())
                 slot = self.b.admit(handle, req.steps, req.tol)
                 if slot is None:       # the engine's own accounting disagrees: wait
                     self.b.release(handle)
+                    geo[req.id] = pool.submit(geometry, req)   # built again for the next try
                     break
-                queue.popleft()
+                del queue[i]
+                for r in blocked:
+                    self.overtaken[r.id] = self.overtaken.get(r.id, 0) + 1
                 active[slot] = (req, handle, self.clock() - t0, nbytes)
                 used += nbytes
             if active:

@@ -74,3 +74,29 @@ def test_committed_profiles_match_the_sources():
             for r in rs if isinstance(rs, list) else [rs]:
                 assert r["source_hash"] == b.kernel_source_hash(), (name, st, r["kernel_bench"])
                 assert b.profile_record(name, st, r["kernel_bench"]) == r
+
+
+def test_reduction_cadence_does_not_follow_the_timed_length():
+    """The FP64 reduction runs every 99 steps (three-step launches) or 100, counted from
+    the start of the run with the warmup, whatever --steps is; segments split at each
+    reduction and at the end of the warmup, whole launches apart from remainders."""
+    b = _bench()
+    assert b.reduction_block(3) == 99 and b.reduction_block(2) == 100 and b.reduction_block(1) == 100
+    # the driver's short run: 5 warmup then 20 timed steps, no reduction falls inside
+    sched = b.run_schedule(20, 5, 3)
+    assert sched == [(False, 3, 2, False), (True, 18, 2, False)]
+    assert sum(w + r for t, w, r, _ in sched if t) == 20
+    assert not any(red for _, _, _, red in sched)
+    # a long run: reductions at 99, 198, ... counted from step 0
+    sched = b.run_schedule(1000, 100, 3)
+    assert sum(w + r for t, w, r, _ in sched if t) == 1000
+    ends, t = [], 0
+    for _, w, r, red in sched:
+        t += w + r
+        if red:
+            ends.append(t)
+    assert ends == list(range(99, 1101, 99))
+    assert all(w % 3 == 0 for _, w, _, _ in sched)
+    # one step per launch: every 100 steps
+    sched = b.run_schedule(250, 50, 1)
+    assert [w for _, w, _, _ in sched] == [50, 50, 100, 100] and [x[3] for x in sched] == [False, True, True, True]

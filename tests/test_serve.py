@@ -201,6 +201,24 @@ def test_request_larger_than_the_budget_is_refused():
     assert s["served"] == 3 and s["states"]["refused"] == 1
 
 
+def test_small_requests_overtake_a_blocked_head_within_a_bound():
+    """A request the free budget cannot hold yet is overtaken by later ones that fit,
+    at most max_overtakes times; then it is reserved and admitted before any later one."""
+    big = Request(id=0, arrival=0.0, kind="cavity", L=20, steps=100, seed=0)
+    long_ = Request(id=1, arrival=0.0, kind="cavity", L=20, steps=2000, seed=1)
+    smalls = [Request(id=10 + k, arrival=0.001 * k, kind="cavity", L=10, steps=100, seed=k) for k in range(12)]
+    budget = (20 * 20 + 12 * 12) * OracleBackend.BYTES_PER_NODE   # one 20^2 grid plus some small ones
+    for cap, expect_before in ((16, 12), (3, 3)):
+        be = OracleBackend(FakeClock(), slots=8, sec_per_lup=1e-6)   # the long grid holds its memory
+        srv = Server(be, budget, 8, burst=50, clock=be.clock, sleep=be.clock.sleep, max_overtakes=cap)
+        res = {r.id: r for r in srv.serve([long_, big] + smalls)}
+        # the long grid holds the budget; the big one waits for it, small ones overtake it
+        before = [r for r in res.values() if r.id >= 10 and r.admitted < res[0].admitted]
+        assert len(before) == expect_before, (cap, len(before))
+        assert srv.overtaken[0] == expect_before
+        assert all(r.state == "budget" for r in res.values())
+
+
 def test_request_stream_shapes():
     reqs = I.request_stream(200, seed=5, rate=2.0)
     assert len(reqs) == 200
