@@ -82,7 +82,9 @@ def parse():
     p.add_argument("--no-serve", action="store_true", help="periodic: skip the serving sub-record")
     p.add_argument("--batched-steps", type=int, default=2000,
                    help="periodic: steps of every cavity in the batched sub-record")
-    p.add_argument("--serve-requests", type=int, default=100, help="periodic: requests of the serving sub-record")
+    p.add_argument("--serve-requests", type=int, default=300, help="periodic: requests of the serving sub-record")
+    p.add_argument("--batched-only", action="store_true",
+                   help="cavities: time the batched form only (profiling runs)")
     p.add_argument("--batch-shape", default=None,
                    help="cavities: fix the batch tile shape, fuse:rows0:rows1:rows2:rows3 (no autotuning)")
     return p.parse_args()

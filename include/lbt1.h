@@ -400,14 +400,16 @@ lbt1_status lbt1_batch_slot_info(lbt1_batch *b, int32_t slot, int32_t *state, in
 enum {
   LBT1_BATCH_FUSE_NONE = 0,   /* every grid one step per launch */
   LBT1_BATCH_FUSE_ALL = 1,    /* every grid whose rows 2 columns per lane fit in the fused class */
-  LBT1_BATCH_FUSE_NARROW = 2  /* the fused class for grids narrower than the 4-column class */
+  LBT1_BATCH_FUSE_MIXED = 2   /* the fused class except for grids of the 4-column class narrower
+                                 than 1024 columns (the default) */
 };
 typedef struct {
   int32_t fuse;     /* LBT1_BATCH_FUSE_* */
   int32_t lds;      /* 1: grids that fit run resident in LDS (class 4); 0: they do not */
   int32_t rows[5];  /* strip height of classes 0..4: 6 or 14 for classes 0-2 and 4; 2, 6,
                        14 or 30 (not 30 in FP64) for class 3; 0 = the library's heuristic
-                       (14 rows where a class has eight or more strips per CU, else 6) */
+                       (14 rows where a class has eight or more strips per CU, else 6;
+                       class 3 30 rows where it has four or more such strips per CU) */
 } lbt1_batch_shape;
 
 /* Take a tile shape for the following bursts.  EINVAL for a shape that is not built. */

@@ -43,8 +43,13 @@ static int class_flips(int c, int k) {
   return k <= 0 ? 0 : kStepsOfClass[c] ? (k + kStepsOfClass[c] - 1) / kStepsOfClass[c] : 1;
 }
 
-// How grids are assigned to classes.
-enum { FUSE_NONE = 0, FUSE_ALL = 1, FUSE_NARROW = 2 };
+// How grids are assigned to classes.  MIXED: the fused class except for grids of
+// the four-column class narrower than kMixedWide columns (measured on the uneven
+// cavities: one step per launch at four columns per lane is faster for sides 256
+// to 512, two steps per launch for narrower grids, as on single grids of 1024
+// and more, where two fused steps win).
+enum { FUSE_NONE = 0, FUSE_ALL = 1, FUSE_MIXED = 2 };
+constexpr int kMixedWide = 1024;
 
 struct Slot {
   lbt1_grid *g = nullptr;
@@ -93,7 +98,7 @@ struct lbt1_batch {
   size_t lds_bytes = 0;                             // dynamic LDS of the LDS-class launch
   size_t lds_limit = 0;                             // most LDS one workgroup may take
   // tile-shape policy: class assignment and fixed strip heights (0 = heuristic)
-  int fuse_mode = lbt1::FUSE_NONE;
+  int fuse_mode = lbt1::FUSE_MIXED;
   bool lds_mode = false;
   int want_rows[lbt1::kClasses] = {};
   bool items_dirty = true;
@@ -129,7 +134,7 @@ static int class_for(const lbt1_batch *b, const Slot &sl) {
       (size_t)lds_grid_bytes(sl.g->nx, sl.g->ny, 2, (int)value_bytes(sl.g->prec)) <= b->lds_limit)
     return CLS_LDS;
   if (b->fuse_mode == FUSE_ALL && fits2) return CLS_F2;
-  if (b->fuse_mode == FUSE_NARROW && fits2 && sl.vclass < CLS_V4) return CLS_F2;
+  if (b->fuse_mode == FUSE_MIXED && fits2 && (sl.vclass < CLS_V4 || sl.g->nx >= kMixedWide)) return CLS_F2;
   return sl.vclass;
 }
 
@@ -160,18 +165,24 @@ static long graph_shape(const lbt1_batch *b) {
 
 static void rebuild_items(lbt1_batch *b) {
   long tall[kClasses] = {};
+  long tall30 = 0;  // fused-class strips at 30 rows
   for (int s = 0; s < b->max_slots; ++s) {
     Slot &sl = b->slots[s];
     if (sl.state == LBT1_SLOT_FREE) continue;
     sl.cls = class_for(b, sl);
     const int v = kVecOfClass[sl.cls];
-    tall[sl.cls] += (long)((chunks_of(sl.g->nx, v) + 61) / 62) * ((sl.g->ny + 13) / 14);
+    const long sx = (chunks_of(sl.g->nx, v) + 61) / 62;
+    tall[sl.cls] += sx * ((sl.g->ny + 13) / 14);
+    if (sl.cls == CLS_F2) tall30 += sx * ((sl.g->ny + 29) / 30);
   }
   for (int c = 0; c < kClasses; ++c) {
     b->items[c].clear();
     // heuristic height: 14-row strips where a class has eight or more per CU,
-    // else 6 (a strip walks its rows one after another)
+    // else 6 (a strip walks its rows one after another); the fused class 30 rows
+    // where it has four or more such strips per CU (the uneven cavities' tuned
+    // choice: fewer halo rows per stored row)
     b->rows[c] = b->want_rows[c] ? b->want_rows[c] : c == CLS_LDS || tall[c] < 8L * b->cus ? 6 : 14;
+    if (c == CLS_F2 && !b->want_rows[c] && tall30 >= 4L * b->cus) b->rows[c] = 30;
     // a height the batch's precision has no kernel for (30 rows in FP64) falls back
     if (b->prec >= 0 && !class_kernel(b, c)) b->rows[c] = 14;
   }
@@ -378,7 +389,7 @@ static lbt1_status launch_burst(lbt1_batch *b, int K, int *nact_out) {
 // Take a tile-shape policy: the class assignment and the strip heights (0 keeps
 // the heuristic); the work lists are rebuilt before the next burst.
 static lbt1_status set_shape(lbt1_batch *b, const lbt1_batch_shape &sh) {
-  if (sh.fuse < FUSE_NONE || sh.fuse > FUSE_NARROW) return fail(LBT1_EINVAL, "fuse mode %d", sh.fuse);
+  if (sh.fuse < FUSE_NONE || sh.fuse > FUSE_MIXED) return fail(LBT1_EINVAL, "fuse mode %d", sh.fuse);
   if (sh.lds != 0 && sh.lds != 1) return fail(LBT1_EINVAL, "lds mode %d", sh.lds);
   for (int c = 0; c < kClasses; ++c) {
     const int r = sh.rows[c];
@@ -627,7 +638,7 @@ lbt1_status lbt1_batch_autotune(lbt1_batch *b, int32_t burst_steps, int32_t reps
   };
   lbt1_batch_shape bestsh{};
   double best_ms = 1e300;
-  const int modes[] = {FUSE_NONE, FUSE_NARROW, FUSE_ALL};
+  const int modes[] = {FUSE_NONE, FUSE_MIXED, FUSE_ALL};
   for (int lds = 0; lds <= 1 && !st; ++lds) {
     for (int mode : modes) {
       if (st) break;
@@ -638,7 +649,7 @@ lbt1_status lbt1_batch_autotune(lbt1_batch *b, int32_t burst_steps, int32_t reps
       for (int s : res) present[class_for(b, b->slots[s])] = true;
       if (lds && !present[CLS_LDS]) continue;
       if (mode != FUSE_NONE && !present[CLS_F2]) continue;
-      if (mode == FUSE_NARROW && !present[CLS_V4]) continue;  // the same classes as FUSE_ALL
+      if (mode == FUSE_MIXED && !present[CLS_V4]) continue;  // the same classes as FUSE_ALL
       lbt1_batch_shape cur{};
       cur.fuse = mode;
       cur.lds = lds;

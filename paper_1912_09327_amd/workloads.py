@@ -31,7 +31,7 @@ def _cavity_grid(L, u, prec):
     return g, (flags, rho, jx, jy)
 
 
-def run_cavities(n, cap, tol, torch, log, burst=100, seed=4, tune=True, shape=None):
+def run_cavities(n, cap, tol, torch, log, burst=100, seed=4, tune=True, shape=None, plain=True):
     """The uneven-cavity population (n cavities, seed 4) run batched and one grid at a
     time, each grid to residual <= tol (tol < 0: never) or cap steps.  The batch's tile
     shape is the autotuner's (tune; its time is not counted), or `shape`
@@ -87,11 +87,11 @@ def run_cavities(n, cap, tol, torch, log, burst=100, seed=4, tune=True, shape=No
 
     # ---- plain: one grid at a time with its own default kernel and graph bursts,
     # the same residual checks every `burst` steps
-    log("[cavities] plain")
+    log("[cavities] plain" if plain else "[cavities] plain form skipped")
     be = GpuBackend(1 << 30, 1, prec="f16s")
     t0 = time.perf_counter()
     same = True
-    for k, (L, u) in enumerate(pop):
+    for k, (L, u) in enumerate(pop if plain else []):
         g, _ = _cavity_grid(L, u, "f16s")
         state, nst, _ = be.run_alone(g, cap, tol, burst)
         same &= nst == steps[k]
@@ -100,14 +100,14 @@ def run_cavities(n, cap, tol, torch, log, burst=100, seed=4, tune=True, shape=No
         g.close()
         if k % 64 == 63:
             log(f"[cavities] plain: {k + 1} grids, {time.perf_counter() - t0:.1f} s")
-    t_plain = time.perf_counter() - t0
+    t_plain = time.perf_counter() - t0 if plain else float("nan")
     be.close()
     mlups_plain = lups_total / t_plain / 1e6
     log(f"[cavities] plain: {t_plain:.2f} s, {mlups_plain:.0f} MLUPS, identical {same}")
 
     # ---- error of the FP16 storage against FP64 runs of the same steps (sample)
     errs = []
-    for k in sample[:4]:
+    for k in sample[:4] if plain else []:
         L, u = pop[k]
         g, (flags, *_r) = _cavity_grid(L, u, "f64")
         g.step(steps[k])
@@ -131,7 +131,8 @@ def bench_cavities(args, torch, log):
     if getattr(args, "batch_shape", None):
         f, *rows = [int(v) for v in args.batch_shape.split(":")]
         shape = (f, rows)
-    r = run_cavities(args.cavities, cap, tol, torch, log, tune=not args.no_tune, shape=shape)
+    r = run_cavities(args.cavities, cap, tol, torch, log, tune=not args.no_tune, shape=shape,
+                     plain=not getattr(args, "batched_only", False))
     return {
         "metric": METRIC,
         "value": r["batched"]["mlups"],
