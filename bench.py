@@ -86,7 +86,8 @@ def parse():
     p.add_argument("--batched-only", action="store_true",
                    help="cavities: time the batched form only (profiling runs)")
     p.add_argument("--batch-shape", default=None,
-                   help="cavities: fix the batch tile shape, fuse:rows0:rows1:rows2:rows3 (no autotuning)")
+                   help="cavities: fix the batch tile shape (no autotuning), "
+                        "fuse:rows0:rows1:rows2:rows3[:rows4[:lds[:vec_cap]]]")
     return p.parse_args()
 
 
@@ -704,7 +705,8 @@ def run_drop(args, torch):
 def run_3d(args, torch):
     """3-D LBMTau1 on periodic random fields (rho = 1 + 1e-3 N(0,1), u = 0.01 N(0,1),
     seed 0): MLUPS and algorithmic GB/s (2 * 4 * c bytes per LUP) for D3Q19 and D3Q27,
-    with device bytes per node against the standard method's (2 Q + 4) c."""
+    with device bytes per node against the standard method's (2 Q + 4) c; and a
+    lid-driven box of the same sides, D3Q19, with the tile and the gather kernel."""
     from paper_1912_09327_amd import _capi as C
     from paper_1912_09327_amd.grid3d import Grid3D
     st = args.storage
@@ -745,6 +747,40 @@ def run_3d(args, torch):
             g.close()
             torch.cuda.empty_cache()
         del rho, js
+    # walled: a lid-driven box (SOLID faces, the top plane FIXED at u = (0.05, 0, 0)),
+    # D3Q19, the tile kernel (its wall-aware form) against one thread per node
+    walled = []
+    for n in [int(v) for v in args.n3.split(",")]:
+        flags = np.zeros((n, n, n), np.uint8)
+        flags[0] = flags[:, 0] = flags[:, -1] = flags[:, :, 0] = flags[:, :, -1] = 1
+        flags[-1, 1:-1, 1:-1] = 2
+        rho = np.ones((n, n, n))
+        jx = np.where(flags == 2, 0.05, 0.0)
+        zero = np.zeros((n, n, n))
+        for kern in ("tile", "gather"):
+            g = Grid3D(n, n, n, q=19, prec=st, periodic=0)
+            g.set_kernel(kern)
+            g.set_geometry(flags, rho, jx, zero, zero)
+            steps = args.steps3 or (200 if n <= 256 else 50)
+            g.step(10)
+            g.sync()
+            s = g.stream
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(s)
+            g.step(steps)
+            b.record(s)
+            torch.cuda.synchronize()
+            kms = a.elapsed_time(b) / steps
+            fluid = float(((flags == 0).sum()))
+            rec = dict(n=n, q=19, kernel=kern, steps=steps, kernel_ms=round(kms, 4),
+                       mlups=round(fluid / (kms * 1e-3) / 1e6, 1),
+                       achieved_GBps=round(2 * 4 * c * n ** 3 / (kms * 1e-3) / 1e9, 1))
+            log(f"[3d] box {n}^3 D3Q19 {kern}: {rec['mlups']:.0f} MLUPS (fluid nodes), {rec['achieved_GBps']:.0f} GB/s")
+            walled.append(rec)
+            g.close()
+            torch.cuda.empty_cache()
+        del flags, rho, jx, zero
     head = max(rows, key=lambda r: (r["n"], r["q"] == 19))
     return {
         "metric": METRIC,
@@ -765,6 +801,7 @@ def run_3d(args, torch):
                      "frac": round(head["achieved_GBps"] / HBM_PEAK_GBPS, 4), "traffic": None,
                      "bytes_per_lup": 2 * 4 * c},
         "runs": rows,
+        "walled": walled,
     }
 
 

@@ -334,11 +334,10 @@ lbt1_status lbt1_grid3d_read_moments(lbt1_grid3d *g, double *rho, double *jx, do
  * 5 non-finite count, 6 FLUID count, 7 zero.  Synchronises. */
 lbt1_status lbt1_grid3d_reduce(lbt1_grid3d *g, uint32_t what, double *out);
 /* Kernel family: LBT1_KERNEL_AUTO (default) and LBT1_KERNEL_STRIP take the tile
- * kernel (a 64 x 4 block marches along z with three planes of per-node values
- * in LDS) on grids periodic in x, y, z without SOLID or FIXED nodes (STRIP:
- * EINVAL elsewhere); LBT1_KERNEL_GATHER one thread per node.  The two give
- * the same bits.  get_kernel reports the family bound (ESTATE before
- * set_geometry). */
+ * kernel (a 64 x 8 block marches along z with three planes of per-node values
+ * in LDS, and their flags on grids with SOLID or FIXED nodes or a non-periodic
+ * axis); LBT1_KERNEL_GATHER one thread per node.  The two give the same bits.
+ * get_kernel reports the family bound (ESTATE before set_geometry). */
 lbt1_status lbt1_grid3d_set_kernel(lbt1_grid3d *g, int32_t kernel);
 lbt1_status lbt1_grid3d_get_kernel(lbt1_grid3d *g, int32_t *kernel);
 lbt1_status lbt1_grid3d_sync(lbt1_grid3d *g);
@@ -410,12 +409,16 @@ typedef struct {
                        14 or 30 (not 30 in FP64) for class 3; 0 = the library's heuristic
                        (14 rows where a class has eight or more strips per CU, else 6;
                        class 3 30 rows where it has four or more such strips per CU) */
+  int32_t vec_cap;  /* widest columns per lane of the one-step classes: 4 (and 0: the
+                       default), 2 or 1; narrower chunks hold fewer registers, so more
+                       wavefronts per SIMD hide memory latency */
 } lbt1_batch_shape;
 
 /* Take a tile shape for the following bursts.  EINVAL for a shape that is not built. */
 lbt1_status lbt1_batch_set_shape(lbt1_batch *b, const lbt1_batch_shape *shape);
 
-/* The fuse mode in force and the strip heights the resident grids run with now. */
+/* The fuse mode, LDS mode and column cap in force and the strip heights the resident
+ * grids run with now. */
 lbt1_status lbt1_batch_get_shape(lbt1_batch *b, lbt1_batch_shape *shape);
 
 /* Time tile shapes on the resident, running grids and keep the fastest: each fuse

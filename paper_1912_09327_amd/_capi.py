@@ -62,10 +62,11 @@ class KernelConfig(ctypes.Structure):
 
 
 class BatchShape(ctypes.Structure):
-    _fields_ = [("fuse", ctypes.c_int32), ("lds", ctypes.c_int32), ("rows", ctypes.c_int32 * 5)]
+    _fields_ = [("fuse", ctypes.c_int32), ("lds", ctypes.c_int32), ("rows", ctypes.c_int32 * 5),
+                ("vec_cap", ctypes.c_int32)]
 
     def as_dict(self):
-        return dict(fuse=self.fuse, lds=self.lds, rows=list(self.rows))
+        return dict(fuse=self.fuse, lds=self.lds, rows=list(self.rows), vec_cap=self.vec_cap)
 
 
 class Grid3DDesc(ctypes.Structure):

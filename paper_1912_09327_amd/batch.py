@@ -33,11 +33,12 @@ class Batch:
     def run(self, burst_steps):
         C.check(C.lib.lbt1_batch_run(self.handle, int(burst_steps)))
 
-    def set_shape(self, fuse=2, rows=(0, 0, 0, 0, 0), lds=0):
+    def set_shape(self, fuse=2, rows=(0, 0, 0, 0, 0), lds=0, vec_cap=0):
         """Tile shape: fuse mode (0 none, 1 all, 2 mixed: the default), LDS residency of
-        small grids (0 / 1) and the strip height of the five work classes (0 = heuristic)."""
+        small grids (0 / 1), the strip height of the five work classes (0 = heuristic)
+        and the widest columns per lane of the one-step classes (4, 2, 1; 0 = 4)."""
         rows = list(rows) + [0] * (5 - len(rows))
-        sh = C.BatchShape(int(fuse), int(lds), (ctypes.c_int32 * 5)(*[int(r) for r in rows]))
+        sh = C.BatchShape(int(fuse), int(lds), (ctypes.c_int32 * 5)(*[int(r) for r in rows]), int(vec_cap))
         C.check(C.lib.lbt1_batch_set_shape(self.handle, ctypes.byref(sh)))
 
     def shape(self):

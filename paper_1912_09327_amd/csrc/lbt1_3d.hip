@@ -82,9 +82,13 @@ constexpr int zchunk_of() {
 static int zchunk_for(int prec) { return prec == P_F16S || prec == P_BF16S ? 16 : 32; }
 constexpr int kTile3Y = 8;   // rows of a tile block (64 x 8 nodes, 512 threads)
 
-static const void *tile3_kernel(int prec, int q) {
-#define T3(P, Q) \
-  if (prec == P && q == Q) return (const void *)&k_step3_tile<P, Q, zchunk_of<P>(), kTile3Y>;
+static const void *tile3_kernel(int prec, int q, bool haswall, int wall) {
+#define T3(P, Q)                                                                                          \
+  if (prec == P && q == Q) {                                                                              \
+    if (!haswall) return (const void *)&k_step3_tile<P, Q, zchunk_of<P>(), kTile3Y>;                     \
+    return wall == WALL_PAPER ? (const void *)&k_step3_tile<P, Q, zchunk_of<P>(), kTile3Y, true, WALL_PAPER> \
+                              : (const void *)&k_step3_tile<P, Q, zchunk_of<P>(), kTile3Y, true, WALL_HALFWAY>; \
+  }
   T3(P_F64, 19) T3(P_F64, 27) T3(P_F32, 19) T3(P_F32, 27) T3(P_F16S, 19) T3(P_F16S, 27) T3(P_BF16S, 19)
   T3(P_BF16S, 27)
 #undef T3
@@ -127,14 +131,11 @@ struct lbt1_grid3d {
   const void *kern = nullptr;
 };
 
-// AUTO and STRIP take the tile kernel on grids periodic in all axes without wall
-// or fixed nodes; GATHER (and AUTO elsewhere) the one-thread-per-node kernel.
+// AUTO and STRIP take the tile kernel (its wall-aware form on grids with SOLID or
+// FIXED nodes or a non-periodic axis); GATHER the one-thread-per-node kernel.
 static lbt1_status bind3(lbt1_grid3d *g) {
-  const bool can_tile = !g->haswall;
-  if (g->want == LBT1_KERNEL_STRIP && !can_tile)
-    return fail(LBT1_EINVAL, "the 3-D tile kernel needs a grid periodic in x, y, z without SOLID or FIXED nodes");
-  g->tile = g->want != LBT1_KERNEL_GATHER && can_tile;
-  g->kern = g->tile ? tile3_kernel(g->prec, g->q) : step3_kernel(g->prec, g->q, g->haswall, g->wall);
+  g->tile = g->want != LBT1_KERNEL_GATHER;
+  g->kern = g->tile ? tile3_kernel(g->prec, g->q, g->haswall, g->wall) : step3_kernel(g->prec, g->q, g->haswall, g->wall);
   if (!g->kern) return fail(LBT1_EINVAL, "no built 3-D kernel");
   return LBT1_OK;
 }

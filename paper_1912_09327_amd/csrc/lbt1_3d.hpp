@@ -178,12 +178,21 @@ __global__ void __launch_bounds__(256) k_step3_gather(Step3Args a) {
   static_cast<S *>(a.dst[3])[i] = T::enc(zn);
 }
 
-// Periodic grids without wall or fixed nodes: a block of 64 x TY nodes marches
-// along z through ZC planes.  Three planes of its tile plus a one-node halo
-// live in LDS as the per-source values every emission needs (J, s = 4.5 / rho,
-// b = d - 1.5 |J|^2 / rho), computed once per node and plane; each target then
-// forms its Q arrivals from LDS.  The per-direction arithmetic is that of the
-// gather kernel, so the two give the same bits.
+// A block of 64 x TY nodes marches along z through ZC planes.  Three planes of
+// its tile plus a one-node halo live in LDS as the per-source values every
+// emission needs (J, s = 4.5 / rho, b = d - 1.5 |J|^2 / rho), computed once per
+// node and plane; each target then forms its Q arrivals from LDS.  The
+// per-direction arithmetic is that of the gather kernel, so the two give the
+// same bits.
+//
+// HASWALL: grids with SOLID or FIXED nodes or a non-periodic axis.  The flags of
+// the three planes sit in LDS beside the values (SOLID for positions outside a
+// non-periodic axis); an arrival from a SOLID source takes the wall rule of the
+// gather kernel -- w_q times the target's own deviation (Eq. feqnoslip; the
+// target's d is carried in registers from the plane it was loaded with) or, with
+// half-way bounce-back, the target's own emission along -e_q from its LDS slot --
+// and a non-FLUID target is not written (it holds its value in both parities).
+// Without walls every axis is periodic and the block wraps.
 //
 // Loading a plane: every thread fills the LDS slot of its own node, and the
 // first 2 (64 + 2) + 2 TY threads each fill one halo-ring slot (the other
@@ -192,7 +201,7 @@ __global__ void __launch_bounds__(256) k_step3_gather(Step3Args a) {
 // are loaded into registers one plane before they go to LDS.
 constexpr int kTile3X = 64;
 
-template <int P, int Q, int ZC, int TY>
+template <int P, int Q, int ZC, int TY, bool HASWALL = false, int WALL = 0>
 __global__ void __launch_bounds__(64 * TY) k_step3_tile(Step3Args a) {
   using T = Traits<P>;
   using C = typename T::C;
@@ -200,15 +209,28 @@ __global__ void __launch_bounds__(64 * TY) k_step3_tile(Step3Args a) {
   constexpr int HX = kTile3X + 2, HY = TY + 2, HN = HX * HY;
   constexpr int RING = 2 * HX + 2 * TY;  // halo slots outside the tile
   __shared__ C sJx[3][HN], sJy[3][HN], sJz[3][HN], sS[3][HN], sB[3][HN];
+  __shared__ uint8_t sF[HASWALL ? 3 : 1][HASWALL ? HN : 1];  // flags (SOLID outside a non-periodic axis)
   const int tid = threadIdx.x;
   const int tx = tid & 63, ty = tid >> 6;
   const int x0 = blockIdx.x * kTile3X, y0 = blockIdx.y * TY, z0 = blockIdx.z * ZC;
   const C Fx = C(a.fx), Fy = C(a.fy), Fz = C(a.fz);
+  const bool px = !HASWALL || (a.periodic & 1u), py = !HASWALL || (a.periodic & 2u),
+             pz = !HASWALL || (a.periodic & 4u);
   const int own_h = (ty + 1) * HX + tx + 1;
-  const long own_off = (long)wrap_axis(y0 + ty, a.ny, true) * a.rs + wrap_axis(x0 + tx, a.nx, true);
+  // in-plane offsets (x, y wrapped on periodic axes); -1: outside a non-periodic axis
+  auto plane_off = [&](const int x, const int y) -> long {
+    const int wx = wrap_axis(x, a.nx, px), wy = wrap_axis(y, a.ny, py);
+    return wx < 0 || wy < 0 ? -1 : (long)wy * a.rs + wx;
+  };
+  auto flag_off = [&](const int x, const int y) -> long {
+    const int wx = wrap_axis(x, a.nx, px), wy = wrap_axis(y, a.ny, py);
+    return wx < 0 || wy < 0 ? -1 : (long)wy * a.pitch + wx;
+  };
+  const long own_off = plane_off(x0 + tx, y0 + ty);
+  const long own_foff = HASWALL ? flag_off(x0 + tx, y0 + ty) : 0;
   const bool has_ring = tid < RING;
   int ring_h = 0;
-  long ring_off = 0;
+  long ring_off = 0, ring_foff = 0;
   if (has_ring) {
     int hx, hy;
     if (tid < HX) {  // row below the tile
@@ -225,15 +247,24 @@ __global__ void __launch_bounds__(64 * TY) k_step3_tile(Step3Args a) {
       hy = 1 + (tid - 2 * HX - TY);
     }
     ring_h = hy * HX + hx;
-    ring_off = (long)wrap_axis(y0 - 1 + hy, a.ny, true) * a.rs + wrap_axis(x0 - 1 + hx, a.nx, true);
+    ring_off = plane_off(x0 - 1 + hx, y0 - 1 + hy);
+    if (HASWALL) ring_foff = flag_off(x0 - 1 + hx, y0 - 1 + hy);
   }
   // plane loads run one plane ahead in registers: the loads of plane z + 2 are
-  // in flight while the targets of plane z are formed
+  // in flight while the targets of plane z are formed.  Positions outside a
+  // non-periodic axis load node 0 and are flagged SOLID.
   C od, ojx, ojy, ojz, rd = C(0), rjx = C(0), rjy = C(0), rjz = C(0);
+  uint8_t ofl = NODE_FLUID, rfl = NODE_FLUID;
   auto fetch = [&](const int z) __attribute__((always_inline)) {
-    const long zo = (long)wrap_axis(z, a.nz, true) * a.zs;
-    load3<P>(a, zo + own_off, od, ojx, ojy, ojz);
-    if (has_ring) load3<P>(a, zo + ring_off, rd, rjx, rjy, rjz);
+    const int wz = wrap_axis(z, a.nz, pz);
+    const long zo = wz < 0 ? 0 : (long)wz * a.zs;
+    load3<P>(a, zo + (own_off < 0 ? 0 : own_off), od, ojx, ojy, ojz);
+    if (has_ring) load3<P>(a, zo + (ring_off < 0 ? 0 : ring_off), rd, rjx, rjy, rjz);
+    if (HASWALL) {
+      const long fz = (long)(wz < 0 ? 0 : wz) * a.fzs;
+      ofl = wz < 0 || own_foff < 0 ? (uint8_t)NODE_SOLID : a.flags[fz + own_foff];
+      if (has_ring) rfl = wz < 0 || ring_foff < 0 ? (uint8_t)NODE_SOLID : a.flags[fz + ring_foff];
+    }
   };
   auto put = [&](const C d, const C jx, const C jy, const C jz, const int slot, const int h)
       __attribute__((always_inline)) {
@@ -250,11 +281,17 @@ __global__ void __launch_bounds__(64 * TY) k_step3_tile(Step3Args a) {
   auto store_plane = [&](const int slot) __attribute__((always_inline)) {
     put(od, ojx, ojy, ojz, slot, own_h);
     if (has_ring) put(rd, rjx, rjy, rjz, slot, ring_h);
+    if (HASWALL) {
+      sF[slot][own_h] = ofl;
+      if (has_ring) sF[slot][ring_h] = rfl;
+    }
   };
   fetch(z0 - 1);
   store_plane(0);
   fetch(z0);
   store_plane(1);
+  C own_d = od;      // the target's own deviation (plane z), for the wall rule
+  uint8_t own_fl = ofl;
   fetch(z0 + 1);
   const int x = x0 + tx, y = y0 + ty;
   const bool out = x < a.nx && y < a.ny;
@@ -262,16 +299,26 @@ __global__ void __launch_bounds__(64 * TY) k_step3_tile(Step3Args a) {
     const int z = z0 + k;
     if (z >= a.nz) break;  // uniform across the block
     store_plane((k + 2) % 3);  // plane z + 1
+    const C next_d = od;
+    const uint8_t next_fl = ofl;
     if (k + 1 < ZC) fetch(z + 2);
     __syncthreads();
-    if (out) {
+    if (out && (!HASWALL || own_fl == NODE_FLUID)) {
       C dn = C(0), xn = C(0), yn = C(0), zn = C(0);
       bool hx = false, hy = false, hz = false;
+      const int cs = (k + 1) % 3;  // the target's own plane
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
         const int slot = (k + 1 - k3z[q] + 3) % 3;  // plane z - e_z
         const int h = (ty + 1 - k3y[q]) * HX + (tx + 1 - k3x[q]);
-        const C f = emit3_sb<C, Q>(q, sJx[slot][h], sJy[slot][h], sJz[slot][h], sS[slot][h], sB[slot][h]);
+        C f = emit3_sb<C, Q>(q, sJx[slot][h], sJy[slot][h], sJz[slot][h], sS[slot][h], sB[slot][h]);
+        if (HASWALL && q != 0 && sF[slot][h] == NODE_SOLID) {
+          if (WALL == WALL_PAPER)
+            f = C(w3<Q>(q)) * own_d;
+          else
+            f = emit3_sb<C, Q>(inv3<Q>(q), sJx[cs][own_h], sJy[cs][own_h], sJz[cs][own_h], sS[cs][own_h],
+                               sB[cs][own_h]);
+        }
         dn = q == 0 ? f : dn + f;
         acc_comp<C>(xn, hx, k3x[q], f);
         acc_comp<C>(yn, hy, k3y[q], f);
@@ -289,6 +336,8 @@ __global__ void __launch_bounds__(64 * TY) k_step3_tile(Step3Args a) {
       static_cast<S *>(a.dst[2])[i] = T::enc(yn);
       static_cast<S *>(a.dst[3])[i] = T::enc(zn);
     }
+    own_d = next_d;
+    own_fl = next_fl;
     __syncthreads();  // the slot of plane z - 1 is refilled next
   }
 }

@@ -24,6 +24,7 @@
 #include <vector>
 
 #include "../../include/lbt1.h"
+#include "lbt1_batch_args.hpp"
 #include "lbt1_internal.hpp"
 #include "lbt1_runtime.hpp"
 
@@ -100,6 +101,7 @@ struct lbt1_batch {
   // tile-shape policy: class assignment and fixed strip heights (0 = heuristic)
   int fuse_mode = lbt1::FUSE_MIXED;
   bool lds_mode = false;
+  int vec_cap_class = lbt1::CLS_V4;  // widest one-step class a grid may take
   int want_rows[lbt1::kClasses] = {};
   bool items_dirty = true;
   hipGraphExec_t graph = nullptr;
@@ -135,7 +137,9 @@ static int class_for(const lbt1_batch *b, const Slot &sl) {
     return CLS_LDS;
   if (b->fuse_mode == FUSE_ALL && fits2) return CLS_F2;
   if (b->fuse_mode == FUSE_MIXED && fits2 && (sl.vclass < CLS_V4 || sl.g->nx >= kMixedWide)) return CLS_F2;
-  return sl.vclass;
+  // the widest one-step class allowed (narrower chunks: fewer registers, more
+  // wavefronts per SIMD to hide memory latency, fewer idle lanes on some widths)
+  return std::min(sl.vclass, b->vec_cap_class);
 }
 
 static const void *class_kernel(const lbt1_batch *b, int c) {
@@ -203,7 +207,9 @@ static void rebuild_items(lbt1_batch *b) {
       b->items[sl.cls].push_back(make_int2(s, 0));
       b->lds_bytes = std::max(b->lds_bytes, (size_t)lds_grid_bytes(sl.g->nx, sl.g->ny, 2, (int)value_bytes(sl.g->prec)));
     } else {
-      for (int k = 0; k < sx * sy; ++k) b->items[sl.cls].push_back(make_int2(s, k));
+      // (slot, 4 * strip + kind); kind 0 (the general wall-aware body) until the
+      // list is classified on the device
+      for (int k = 0; k < sx * sy; ++k) b->items[sl.cls].push_back(make_int2(s, k << 2));
     }
     const long nodes = (long)sl.g->nx * sl.g->ny;
     const int chunks = (int)((nodes + kBatchReduceChunk - 1) / kBatchReduceChunk);
@@ -360,6 +366,7 @@ static lbt1_status launch_burst(lbt1_batch *b, int K, int *nact_out) {
   *nact_out = nact;
   if (nact == 0) return LBT1_OK;
   b->h_counts[kCntActive] = nact;
+  const bool rebuilt = b->items_dirty;
   if (b->items_dirty) {
     rebuild_items(b);
     lbt1_status st = upload_items(b);
@@ -378,6 +385,23 @@ static lbt1_status launch_burst(lbt1_batch *b, int K, int *nact_out) {
       (e = hipMemcpyAsync(b->d_active, b->h_active, (size_t)nact * sizeof(int), hipMemcpyHostToDevice, b->stream)) != hipSuccess ||
       (e = hipMemcpyAsync(b->d_counts, b->h_counts, 8 * sizeof(int), hipMemcpyHostToDevice, b->stream)) != hipSuccess)
     return hip_fail(e, "descriptor H2D");
+  if (rebuilt) {
+    // the kind of every strip of the new lists (stream-ordered before the burst)
+    for (int c = 0; c < kClasses; ++c) {
+      if (c == CLS_LDS || b->items[c].empty()) continue;
+      BatchClassifyArgs ca;
+      ca.grids = b->d_grids;
+      ca.items = b->d_items[c];
+      ca.count = b->d_counts + c;
+      ca.rows = b->rows[c];
+      ca.halo = kStepsOfClass[c];
+      void *args[] = {&ca};
+      const int blocks = (int)std::min<long>(((long)b->items[c].size() + 3) / 4, 8L * b->cus);
+      if ((e = hipLaunchKernel(batch_classify_kernel(kVecOfClass[c]), dim3(std::max(1, blocks)), dim3(256), args, 0,
+                               b->stream)) != hipSuccess)
+        return hip_fail(e, "strip classification");
+    }
+  }
   if (!b->graph_valid || b->graph_K != K || b->graph_mask != mask || b->graph_shape != graph_shape(b)) {
     lbt1_status st = build_graph(b, K, mask);
     if (st) return st;
@@ -391,6 +415,8 @@ static lbt1_status launch_burst(lbt1_batch *b, int K, int *nact_out) {
 static lbt1_status set_shape(lbt1_batch *b, const lbt1_batch_shape &sh) {
   if (sh.fuse < FUSE_NONE || sh.fuse > FUSE_MIXED) return fail(LBT1_EINVAL, "fuse mode %d", sh.fuse);
   if (sh.lds != 0 && sh.lds != 1) return fail(LBT1_EINVAL, "lds mode %d", sh.lds);
+  if (sh.vec_cap != 0 && sh.vec_cap != 1 && sh.vec_cap != 2 && sh.vec_cap != 4)
+    return fail(LBT1_EINVAL, "vec_cap %d (0, 1, 2 or 4)", sh.vec_cap);
   for (int c = 0; c < kClasses; ++c) {
     const int r = sh.rows[c];
     if (r == 0) continue;
@@ -400,6 +426,7 @@ static lbt1_status set_shape(lbt1_batch *b, const lbt1_batch_shape &sh) {
   }
   b->fuse_mode = sh.fuse;
   b->lds_mode = sh.lds != 0;
+  b->vec_cap_class = sh.vec_cap == 1 ? CLS_V1 : sh.vec_cap == 2 ? CLS_V2 : CLS_V4;
   for (int c = 0; c < kClasses; ++c) b->want_rows[c] = sh.rows[c];
   b->items_dirty = true;
   return LBT1_OK;
@@ -575,6 +602,7 @@ lbt1_status lbt1_batch_get_shape(lbt1_batch *b, lbt1_batch_shape *shape) {
   shape->fuse = b->fuse_mode;
   shape->lds = b->lds_mode ? 1 : 0;
   for (int c = 0; c < kClasses; ++c) shape->rows[c] = b->rows[c];
+  shape->vec_cap = kVecOfClass[b->vec_cap_class];
   return LBT1_OK;
 }
 
@@ -615,6 +643,7 @@ lbt1_status lbt1_batch_autotune(lbt1_batch *b, int32_t burst_steps, int32_t reps
   }
   const int saved_mode = b->fuse_mode;
   const bool saved_lds = b->lds_mode;
+  const int saved_cap = b->vec_cap_class;
   int saved_rows[kClasses];
   std::memcpy(saved_rows, b->want_rows, sizeof saved_rows);
   hipEvent_t e0, e1;
@@ -639,20 +668,34 @@ lbt1_status lbt1_batch_autotune(lbt1_batch *b, int32_t burst_steps, int32_t reps
   lbt1_batch_shape bestsh{};
   double best_ms = 1e300;
   const int modes[] = {FUSE_NONE, FUSE_MIXED, FUSE_ALL};
+  for (int cap = CLS_V4; cap >= CLS_V2 && !st; --cap)
   for (int lds = 0; lds <= 1 && !st; ++lds) {
     for (int mode : modes) {
       if (st) break;
       // classes the grids take under this policy
       b->fuse_mode = mode;
       b->lds_mode = lds != 0;
-      bool present[kClasses] = {};
-      for (int s : res) present[class_for(b, b->slots[s])] = true;
+      b->vec_cap_class = CLS_V4;
+      bool present[kClasses] = {}, wide = false;
+      for (int s : res) {
+        const int c = class_for(b, b->slots[s]);
+        present[c] = true;
+        wide |= c == CLS_V4;
+      }
       if (lds && !present[CLS_LDS]) continue;
       if (mode != FUSE_NONE && !present[CLS_F2]) continue;
       if (mode == FUSE_MIXED && !present[CLS_V4]) continue;  // the same classes as FUSE_ALL
+      if (cap < CLS_V4) {
+        // narrower chunks for the four-column grids: only where some grid has them
+        if (!wide) continue;
+        b->vec_cap_class = cap;
+        for (int c = 0; c < kClasses; ++c) present[c] = false;
+        for (int s : res) present[class_for(b, b->slots[s])] = true;
+      }
       lbt1_batch_shape cur{};
       cur.fuse = mode;
       cur.lds = lds;
+      cur.vec_cap = kVecOfClass[cap];
       double cur_ms = time_shape(cur);
       // coordinate descent over the strip height of each class present
       for (int c = 0; c < kClasses && !st; ++c) {
@@ -689,6 +732,7 @@ lbt1_status lbt1_batch_autotune(lbt1_batch *b, int32_t burst_steps, int32_t reps
   if (st || er != hipSuccess || best_ms >= 1e300) {
     b->fuse_mode = saved_mode;
     b->lds_mode = saved_lds;
+    b->vec_cap_class = saved_cap;
     std::memcpy(b->want_rows, saved_rows, sizeof saved_rows);
     b->items_dirty = true;
     if (st) return st;

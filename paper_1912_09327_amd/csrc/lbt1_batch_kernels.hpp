@@ -3,8 +3,296 @@
 // and grid descriptors as k_step_batch, with the arithmetic and its order of the
 // single-grid kernels, so every grid gets the bits it would get alone.
 #pragma once
+#include "lbt1_batch_args.hpp"
 #include "lbt1_fused.hpp"
 #include "lbt1_fused_wall.hpp"
+#include "lbt1_step.hpp"
+
+namespace lbt1 {
+
+// ================================================================ batched step
+
+
+// Step arguments of a resident grid reading parity p.
+__device__ __forceinline__ StepArgs batch_step_args(const BatchGrid &g, const int p) {
+  StepArgs a;
+  for (int q = 0; q < 3; ++q) {
+    a.src[q] = g.plane[p][q];
+    a.dst[q] = g.plane[1 - p][q];
+  }
+  a.flags = g.flags;
+  a.nx = g.nx;
+  a.ny = g.ny;
+  a.pitch = g.pitch;
+  a.rs = g.rs;
+  a.periodic = g.periodic;
+  a.fx = g.fx;
+  a.fy = g.fy;
+  a.sc_d = g.sc_d;
+  a.sc_j = g.sc_j;
+  a.is_d = g.is_d;
+  a.is_j = g.is_j;
+  a.trash = g.trash;
+  a.sc_G = 0.0;
+  a.sc_rho0 = 1.0;
+  return a;
+}
+
+// True when every node whose emissions reach a stored node of the strip at
+// (chunk0, y0) through HALO steps is a FLUID node inside the grid: the stored
+// chunks [chunk0, min(nch, chunk0 + 62)) widened by HALO columns on either side
+// and its NY rows widened by HALO rows above and below, with no row or column
+// across an axis.  Such a strip takes the wall-free body, which gives the same bits
+// (the wall rule only ever replaces arrivals from SOLID sources, and the sums run
+// in the same order).  The halo lanes' other columns feed only nodes that are not
+// stored.  HALO <= VEC.  Wave-uniform: the flags are OR-ed per lane, then voted.
+template <int VEC>
+__device__ __forceinline__ bool strip_interior(const StepArgs &a, const int chunk0, const int y0, const int NY,
+                                               const int HALO) {
+  const int nch = (a.nx + VEC - 1) / VEC;
+  const int ce = min(nch, chunk0 + 62);
+  if (chunk0 < 1 || ce <= chunk0 || ce * VEC + HALO > a.nx || y0 < HALO || y0 + NY + HALO > a.ny) return false;
+  const int lane = threadIdx.x & 63;
+  const int ch = chunk0 - 1 + lane;
+  // columns [lo, hi) of this lane's chunk that the stored nodes draw on
+  const int lo = ch == chunk0 - 1 ? VEC - HALO : 0;
+  const int hi = ch == ce ? HALO : (ch < ce ? VEC : 0);
+  uint32_t any = 0;
+  if (hi > lo) {
+    // ch <= ce and ce * VEC < nx, so the pack lies inside the row's pitch
+    const uint8_t *f = a.flags + (long)(y0 - HALO) * a.pitch + (long)ch * VEC;
+    for (int i = 0; i < NY + 2 * HALO; ++i) {
+      const Pack<uint8_t, VEC> p = *reinterpret_cast<const Pack<uint8_t, VEC> *>(f + (long)i * a.pitch);
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) any |= (v >= lo && v < hi) ? p.v[v] : 0u;
+    }
+  }
+  return __ballot(any != 0) == 0;
+}
+
+// True when the flags the wall-aware strip body loads for the strip at (chunk0,
+// y0) -- rows y0 - HALO .. y0 + NY + HALO - 1 of its 64 lanes' chunks, wrapped on a
+// periodic axis, SOLID outside a non-periodic x -- are the same in every row of
+// each column, and no row lies across a non-periodic y.  The body may then take the
+// flags of one row for all (COLF).  Wave-uniform.
+template <int VEC>
+__device__ __forceinline__ bool strip_colwall(const StepArgs &a, const int chunk0, const int y0, const int NY,
+                                              const int HALO) {
+  const bool py = a.periodic & 2u;
+  if (!py && (y0 < HALO || y0 + NY + HALO > a.ny)) return false;
+  const int lane = threadIdx.x & 63;
+  const int nch = (a.nx + VEC - 1) / VEC;
+  const int ch = chunk0 - 1 + lane;
+  int chw = ch;
+  bool col_ok = true;
+  if (ch < 0 || ch >= nch) {
+    if (a.periodic & 1u)
+      chw = ((ch % nch) + nch) % nch;
+    else
+      col_ok = false;  // read as SOLID in every row
+  }
+  uint32_t diff = 0;
+  if (col_ok) {
+    const uint8_t *f = a.flags + (long)chw * VEC;
+    const Pack<uint8_t, VEC> p0 =
+        *reinterpret_cast<const Pack<uint8_t, VEC> *>(f + (long)wrap_axis(y0 - HALO, a.ny, py) * a.pitch);
+    for (int i = 1; i < NY + 2 * HALO; ++i) {
+      const int rr = wrap_axis(y0 - HALO + i, a.ny, py);
+      const Pack<uint8_t, VEC> p = *reinterpret_cast<const Pack<uint8_t, VEC> *>(f + (long)rr * a.pitch);
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) diff |= (uint32_t)(p.v[v] ^ p0.v[v]);
+    }
+  }
+  return __ballot(diff != 0) == 0;
+}
+
+// The kind of each strip of a work list: interior (the wall-free body), column
+// walls (the wall-aware body with the flags of one row) or neither.  A strip's
+// geometry does not change while its grid is resident, so this runs once per work
+// list instead of in every step.  One wavefront per item.
+template <int VEC>
+__global__ void __launch_bounds__(256) k_batch_classify(BatchClassifyArgs b) {
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int n = *b.count;
+  for (int it = blockIdx.x * 4 + wave; it < n; it += gridDim.x * 4) {
+    const int2 item = b.items[it];
+    const BatchGrid &g = b.grids[item.x];
+    const StepArgs a = batch_step_args(g, 0);
+    const int strip = item.y >> 2;
+    const int sy = strip / g.strips_x;
+    const int sx = strip - sy * g.strips_x;
+    const int c0 = sx * 62, y0 = sy * b.rows;
+    const int kind = strip_interior<VEC>(a, c0, y0, b.rows, b.halo)  ? STRIP_INTERIOR
+                     : strip_colwall<VEC>(a, c0, y0, b.rows, b.halo) ? STRIP_COLUMN_WALLS
+                                                                      : STRIP_WALLS;
+    if ((threadIdx.x & 63) == 0) b.items[it].y = (strip << 2) | kind;
+  }
+}
+
+// The one-step strip bodies of a batched grid by the strip's kind: wall-free for
+// interior strips, the wall-aware body with the flags of one row where walls run
+// down whole columns, else the general wall-aware body.  All give the bits of the
+// single-grid kernels.
+template <int P, int VEC, int NY>
+__device__ __forceinline__ void batch_strip(const BatchGrid &g, const StepArgs &a, const int kind, const int c0,
+                                            const int y0, const int lane) {
+  // unit storage scales (the default; a wave-uniform test): the bodies without
+  // the scaling multiplications, which are exact no-ops then
+  const bool unit = !Traits<P>::kScaled || (g.sc_d == 1.0 && g.sc_j == 1.0 && g.is_d == 1.0 && g.is_j == 1.0);
+  if (kind == STRIP_INTERIOR) {
+    if (unit)
+      strip_body<P, false, 0, VEC, NY, true>(a, c0, y0, lane);
+    else
+      strip_body<P, false, 0, VEC, NY, false>(a, c0, y0, lane);
+  } else if (kind == STRIP_COLUMN_WALLS) {
+    if (g.wall == WALL_PAPER) {
+      if (unit)
+        strip_body<P, true, WALL_PAPER, VEC, NY, true, true>(a, c0, y0, lane);
+      else
+        strip_body<P, true, WALL_PAPER, VEC, NY, false, true>(a, c0, y0, lane);
+    } else {
+      if (unit)
+        strip_body<P, true, WALL_HALFWAY, VEC, NY, true, true>(a, c0, y0, lane);
+      else
+        strip_body<P, true, WALL_HALFWAY, VEC, NY, false, true>(a, c0, y0, lane);
+    }
+  } else if (g.wall == WALL_PAPER) {
+    if (unit)
+      strip_body<P, true, WALL_PAPER, VEC, NY, true>(a, c0, y0, lane);
+    else
+      strip_body<P, true, WALL_PAPER, VEC, NY, false>(a, c0, y0, lane);
+  } else {
+    if (unit)
+      strip_body<P, true, WALL_HALFWAY, VEC, NY, true>(a, c0, y0, lane);
+    else
+      strip_body<P, true, WALL_HALFWAY, VEC, NY, false>(a, c0, y0, lane);
+  }
+}
+
+// One wavefront per work item, grid-stride over all items of every grid with
+// columns per lane VEC.
+template <int P, int VEC, int NY>
+__global__ void __launch_bounds__(256) k_step_batch(BatchStepArgs b) {
+  const int lane = threadIdx.x & 63;
+  // wave-uniform as the compiler sees it: the item, its grid's descriptor and the
+  // step arguments are then scalar loads held in scalar registers
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int n = *b.count;
+  for (int it = blockIdx.x * 4 + wave; it < n; it += gridDim.x * 4) {
+    const int2 item = b.items[it];
+    const BatchGrid &g = b.grids[item.x];
+    if (b.step >= g.steps_left) continue;
+    const StepArgs a = batch_step_args(g, (g.parity0 + b.step) & 1);
+    const int strip = item.y >> 2;
+    const int sy = strip / g.strips_x;   // along each row band, as in k_step_strip
+    const int sx = strip - sy * g.strips_x;
+    batch_strip<P, VEC, NY>(g, a, item.y & 3, sx * 62, sy * NY, lane);
+  }
+}
+
+
+template <int P>
+__global__ void __launch_bounds__(256) k_reduce_batch(BatchReduceArgs b) {
+  using T = Traits<P>;
+  using S = typename T::S;
+  const int n = *b.nitems;
+  __shared__ double part[4][6];
+  for (int it = blockIdx.x; it < n; it += gridDim.x) {
+    const int2 item = b.items[it];
+    const int slot = item.x;
+    const BatchGrid &g = b.grids[slot];
+    if (g.steps_left == 0) continue;  // not stepped in this burst (uniform in the block)
+    const int p = (g.parity0 + g.flips) & 1;
+    const S *c0 = static_cast<const S *>(g.plane[p][0]);
+    const S *c1 = static_cast<const S *>(g.plane[p][1]);
+    const S *c2 = static_cast<const S *>(g.plane[p][2]);
+    S *n0 = static_cast<S *>(b.snaps[slot * 3 + 0]);
+    S *n1 = static_cast<S *>(b.snaps[slot * 3 + 1]);
+    S *n2 = static_cast<S *>(b.snaps[slot * 3 + 2]);
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    const long nn = (long)g.nx * g.ny;
+    const long m0 = (long)item.y * kBatchReduceChunk;
+    const long m1 = min(nn, m0 + kBatchReduceChunk);
+    for (long m = m0 + threadIdx.x; m < m1; m += blockDim.x) {
+      const int y = (int)(m / g.nx);
+      const int x = (int)(m - (long)y * g.nx);
+      const long i = (long)y * g.rs + x;
+      if (g.flags[(long)y * g.pitch + x] != NODE_FLUID) continue;
+      const S r0 = c0[i], r1 = c1[i], r2 = c2[i];
+      const double d = (double)T::dec(r0) * g.sc_d;
+      const double jx = (double)T::dec(r1) * g.sc_j;
+      const double jy = (double)T::dec(r2) * g.sc_j;
+      acc[0] += d;
+      acc[1] += jx;
+      acc[2] += jy;
+      acc[4] += (__builtin_isfinite(d) && __builtin_isfinite(jx) && __builtin_isfinite(jy)) ? 0.0 : 1.0;
+      acc[5] += 1.0;
+      const double rho = 1.0 + d;
+      const double sr = 1.0 + (double)T::dec(n0[i]) * g.sc_d;
+      const double su = (double)T::dec(n1[i]) * g.sc_j / sr;
+      const double sv = (double)T::dec(n2[i]) * g.sc_j / sr;
+      acc[3] = __builtin_fmax(acc[3], __builtin_fmax(__builtin_fabs(jx / rho - su), __builtin_fabs(jy / rho - sv)));
+      n0[i] = r0;
+      n1[i] = r1;
+      n2[i] = r2;
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+#pragma unroll
+      for (int q = 0; q < 6; ++q) {
+        const double o = __shfl_xor(acc[q], off);
+        acc[q] = q == 3 ? __builtin_fmax(acc[q], o) : acc[q] + o;
+      }
+    }
+    const int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+      for (int q = 0; q < 6; ++q) part[wave][q] = acc[q];
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+      const int q = threadIdx.x;
+      double v = part[0][q];
+      for (int w = 1; w < (int)(blockDim.x >> 6); ++w) v = q == 3 ? __builtin_fmax(v, part[w][q]) : v + part[w][q];
+      b.partials[(long)it * 6 + q] = v;
+    }
+    __syncthreads();
+  }
+}
+
+// The partials of each active grid (fixed order: lane-strided, then a butterfly)
+// into out[slot * 6 + q].
+__global__ void __launch_bounds__(64) k_reduce_batch_final(BatchReduceArgs b) {
+  const int n = *b.nactive;
+  for (int k = blockIdx.x; k < n; k += gridDim.x) {
+    const int slot = b.active[k];
+    const int2 r = b.ranges[slot];
+    // lane l: partial rows l, l + 64, ... of the grid in order, then a fixed butterfly
+    const int l = threadIdx.x;
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (int i = l; i < r.y; i += 64) {
+#pragma unroll
+      for (int q = 0; q < 6; ++q) {
+        const double x = b.partials[(long)(r.x + i) * 6 + q];
+        acc[q] = q == 3 ? __builtin_fmax(acc[q], x) : acc[q] + x;
+      }
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+#pragma unroll
+      for (int q = 0; q < 6; ++q) {
+        const double o = __shfl_xor(acc[q], off);
+        acc[q] = q == 3 ? __builtin_fmax(acc[q], o) : acc[q] + o;
+      }
+    }
+    if (l == 0) {
+#pragma unroll
+      for (int q = 0; q < 6; ++q) b.out[slot * 6 + q] = acc[q];
+    }
+  }
+}
+
+}  // namespace lbt1
 
 namespace lbt1 {
 
@@ -15,7 +303,7 @@ namespace lbt1 {
 template <int P, int NY>
 __global__ void __launch_bounds__(256) k_step_batch_fused(BatchStepArgs b) {
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // (see k_step_batch)
   const int n = *b.count;
   for (int it = blockIdx.x * 4 + wave; it < n; it += gridDim.x * 4) {
     const int2 item = b.items[it];
@@ -23,12 +311,13 @@ __global__ void __launch_bounds__(256) k_step_batch_fused(BatchStepArgs b) {
     const int left = g.steps_left - 2 * b.step;  // steps this grid still takes in the burst
     if (left <= 0) continue;
     const StepArgs a = batch_step_args(g, (g.parity0 + b.step) & 1);
-    const int sy = item.y / g.strips_x;  // along each row band, as in k_step_strip
-    const int sx = item.y - sy * g.strips_x;
+    const int strip = item.y >> 2;
+    const int sy = strip / g.strips_x;  // along each row band, as in k_step_strip
+    const int sx = strip - sy * g.strips_x;
     // unit storage scales (the default; a wave-uniform test): the bodies without
     // the scaling multiplications, which are exact no-ops then
     const bool unit = !Traits<P>::kScaled || (g.sc_d == 1.0 && g.sc_j == 1.0 && g.is_d == 1.0 && g.is_j == 1.0);
-    if (left >= 2 && strip_interior<2>(a, sx * 62, sy * NY, NY, 2)) {
+    if (left >= 2 && (item.y & 3) == STRIP_INTERIOR) {
       // no wall, fixed node or grid edge within two rows and a lane: the wall-free
       // two-step body (same bits)
       if (unit)

@@ -28,6 +28,7 @@ const void *batch_step_kernel(int prec, int vec_class, int rows);
 const void *batch_fused_kernel(int prec, int rows);  // two steps per launch, two columns per lane
 const void *batch_lds_kernel(int prec, int rows);    // grids resident in LDS for a burst
 const void *batch_reduce_kernel(int prec);
+const void *batch_classify_kernel(int vec);          // strip kinds of a work list, once per list
 const void *batch_reduce_final_kernel();
 
 }  // namespace lbt1

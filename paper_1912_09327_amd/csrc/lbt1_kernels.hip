@@ -233,6 +233,15 @@ const void *batch_lds_kernel(int prec, int rows) {
   return nullptr;
 }
 
+const void *batch_classify_kernel(int vec) {
+  switch (vec) {
+    case 1: return (const void *)&k_batch_classify<1>;
+    case 2: return (const void *)&k_batch_classify<2>;
+    case 4: return (const void *)&k_batch_classify<4>;
+  }
+  return nullptr;
+}
+
 const void *batch_reduce_final_kernel() { return (const void *)&k_reduce_batch_final; }
 
 const void *batch_reduce_kernel(int prec) {

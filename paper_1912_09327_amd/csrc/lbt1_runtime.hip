@@ -257,11 +257,14 @@ const StepKernel *find_kernel(int prec, bool haswall, int wall, int kind, int ve
 }
 
 static std::mutex g_tune_mu;
-static std::map<std::tuple<int, int, int, int, int>, lbt1_kernel_config> g_tuned;
+static std::map<std::tuple<int, int, int, int, int, int>, lbt1_kernel_config> g_tuned;
 
-static std::tuple<int, int, int, int, int> tune_key(const lbt1_grid *g) {
-  // multiphase grids tune separately (precision code offset by 8)
-  return std::make_tuple(g->prec + (g->mp ? 8 : 0), (int)g->haswall, g->haswall ? g->wall : 0, g->nx, g->ny);
+static std::tuple<int, int, int, int, int, int> tune_key(const lbt1_grid *g) {
+  // multiphase grids tune separately (precision code offset by 8); the periodic
+  // bits take part because a strip shape that fits a walled grid of odd width
+  // does not fit one periodic in x
+  return std::make_tuple(g->prec + (g->mp ? 8 : 0), (int)g->haswall, g->haswall ? g->wall : 0, (int)(g->periodic & 3u),
+                         g->nx, g->ny);
 }
 
 // Default without a tuned entry: the gather kernel for tiny grids, else the
@@ -400,9 +403,18 @@ lbt1_status bind_config(lbt1_grid *g, const lbt1_kernel_config &want, int cus) {
   }
   lbt1_kernel_config c = want;
   if (c.kernel == LBT1_KERNEL_AUTO) {
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    auto it = g_tuned.find(tune_key(g));
-    c = it != g_tuned.end() ? it->second : heuristic_config(g->prec, g->haswall, g->wall, g->nx, g->ny, cus, g->mp, g->periodic & 1u);
+    lbt1_kernel_config tuned{};
+    bool have = false;
+    {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      auto it = g_tuned.find(tune_key(g));
+      if (it != g_tuned.end()) tuned = it->second, have = true;
+    }
+    // a tuned entry that does not bind this grid (it should always, being keyed on
+    // everything bind_config checks) yields to the heuristic rather than failing
+    if (have && bind_config(g, tuned, cus) == LBT1_OK) return LBT1_OK;
+    if (have) clear_error();
+    c = heuristic_config(g->prec, g->haswall, g->wall, g->nx, g->ny, cus, g->mp, g->periodic & 1u);
   }
   const StepKernel *k = nullptr, *k1 = nullptr, *k2 = nullptr;
   if (c.kernel == LBT1_KERNEL_GATHER) {

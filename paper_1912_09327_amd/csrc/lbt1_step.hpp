@@ -107,7 +107,15 @@ constexpr int kPrefetch = 2;
 // at the same time.
 // UNIT: both storage scales are 1 (the default), so the codec's scaling
 // multiplications are exact no-ops and are left out.
-template <int P, bool HASWALL, int WALL, int VEC, int NY, bool UNIT = false>
+// COLF (with HASWALL): the caller has checked that every column of the strip's
+// footprint carries the same flags in all of its rows (walls that run down whole
+// columns, as a grid's sides do away from its top and bottom rows).  The flags are
+// then read from one row; whether the columns to the left and right of a column are
+// walls, and whether the column is FLUID, is known once for the whole strip; and the
+// arrivals from the node's own column (straight up and down) are never from a wall
+// when the node is FLUID, so only the six arrivals from the neighbouring columns go
+// through a select.  Same values summed in the same order: same bits.
+template <int P, bool HASWALL, int WALL, int VEC, int NY, bool UNIT = false, bool COLF = false>
 __device__ __forceinline__ void strip_body(const StepArgs &a, const int chunk0, const int y0,
                                            const int lane) {
   using T = Traits<P>;
@@ -173,18 +181,71 @@ __device__ __forceinline__ void strip_body(const StepArgs &a, const int chunk0, 
     dst.raw[0] = *reinterpret_cast<const SP *>(s0 + idx);
     dst.raw[1] = *reinterpret_cast<const SP *>(s1 + idx);
     dst.raw[2] = *reinterpret_cast<const SP *>(s2 + idx);
-    if (HASWALL) {
+    if (HASWALL && !COLF) {
       const FP f = *reinterpret_cast<const FP *>(a.flags + row * pitch + col);
 #pragma unroll
       for (int v = 0; v < VEC; ++v) dst.fl.v[v] = (row_ok && col_ok) ? f.v[v] : (uint8_t)NODE_SOLID;
     }
   };
 
+  // the flags of every row of a COLF strip: those of its first row
+  FP cfl;
+  if (HASWALL && COLF) {
+    const int rr = wrap_axis(y0 - 1, ny, py);
+    const FP f = *reinterpret_cast<const FP *>(a.flags + (long)(rr >= 0 ? rr : 0) * pitch + xc);
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) cfl.v[v] = col_ok ? f.v[v] : (uint8_t)NODE_SOLID;
+  }
+  (void)cfl;
+  // COLF: the column left of column v is a wall (cwl), the one right of it (cwr),
+  // column v is FLUID (cfo)
+  bool cwl[VEC], cwr[VEC], cfo[VEC];
+  if constexpr (HASWALL && COLF) {
+    uint32_t sb = 0;
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) {
+      sb |= (uint32_t)(cfl.v[v] == NODE_SOLID) << v;
+      cfo[v] = cfl.v[v] == NODE_FLUID;
+    }
+    const int Ls = lane_left<P>((int)((sb >> (VEC - 1)) & 1u));
+    const int Rs = lane_right<P>((int)(sb & 1u));
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) {
+      cwl[v] = v > 0 ? ((sb >> (v - 1)) & 1u) != 0 : Ls != 0;
+      cwr[v] = v < VEC - 1 ? ((sb >> (v + 1)) & 1u) != 0 : Rs != 0;
+    }
+  }
+  (void)cwl;
+  (void)cwr;
+  (void)cfo;
+  // COLF: non-FLUID columns keep their stored values.  Where a chunk's values fill
+  // whole 32-bit words, that is a blend of each word of the new values with the old
+  // under a mask formed once (the 16-bit values stay packed); else one select each.
+  constexpr bool kWordBlend = (sizeof(S) * VEC) % 4 == 0;
+  constexpr int kWords = kWordBlend ? (int)(sizeof(S) * VEC / 4) : 1;
+  uint32_t ckeep[kWords];
+  if constexpr (HASWALL && COLF && kWordBlend) {
+#pragma unroll
+    for (int w = 0; w < kWords; ++w) {
+      uint32_t m = 0;
+#pragma unroll
+      for (int v = 0; v < VEC; ++v) {
+        const int b0 = v * (int)sizeof(S), b1 = b0 + (int)sizeof(S);  // bytes of value v
+        if (b0 < 4 * (w + 1) && b1 > 4 * w && !cfo[v]) {
+          const int lo = (b0 > 4 * w ? b0 - 4 * w : 0) * 8, hi = (b1 < 4 * (w + 1) ? b1 - 4 * w : 4) * 8;
+          m |= (hi - lo == 32 ? 0xffffffffu : ((1u << (hi - lo)) - 1u)) << lo;
+        }
+      }
+      ckeep[w] = m;
+    }
+  }
+  (void)ckeep;
+
   // Row i is processed while the loads of the following PF rows are in flight.
   auto body = [&](const int i, Arr &up_old, const Row &cur) __attribute__((always_inline)) {
     const int r = y0 - 1 + i;
     const SP *raw = cur.raw;
-    const FP &fl = cur.fl;
+    const FP &fl = COLF ? cfl : cur.fl;
     C f[VEC][9];
     C dd[VEC];
     uint32_t sbits = 0, fbits = 0;
@@ -198,7 +259,7 @@ __device__ __forceinline__ void strip_body(const StepArgs &a, const int chunk0, 
       }
       dd[v] = d;
       emit<C>(d, jx, jy, Fx, Fy, f[v]);
-      if (HASWALL) {
+      if (HASWALL && !COLF) {
         sbits |= (uint32_t)(fl.v[v] == NODE_SOLID) << v;
         fbits |= (uint32_t)(fl.v[v] == NODE_FLUID) << v;
       }
@@ -214,7 +275,7 @@ __device__ __forceinline__ void strip_body(const StepArgs &a, const int chunk0, 
     const C R6 = lane_right<P>(f[0][6]);
     const C R7 = lane_right<P>(f[0][7]);
     int Ls = 0, Rs = 0;
-    if (HASWALL) {
+    if (HASWALL && !COLF) {
       Ls = lane_left<P>((int)((sbits >> (VEC - 1)) & 1u));
       Rs = lane_right<P>((int)(sbits & 1u));
     }
@@ -248,15 +309,31 @@ __device__ __forceinline__ void strip_body(const StepArgs &a, const int chunk0, 
             w4 = own_f[2][v];
             w7 = own_f[5][v];
           }
-          const C g5 = (ub & 1u) ? w5 : up_old.a[0][v];
-          const C g2 = (ub & 2u) ? w2 : up_old.a[1][v];
-          const C g6 = (ub & 4u) ? w6 : up_old.a[2][v];
-          const C g1 = (lb & 1u) ? w1 : lev.a[0][v];
+          C g5, g2, g6, g1, g3, g8, g4, g7;
+          if constexpr (COLF) {
+            (void)ub;
+            (void)lb;
+            (void)w2;
+            (void)w4;
+            g5 = cwl[v] ? w5 : up_old.a[0][v];
+            g2 = up_old.a[1][v];
+            g6 = cwr[v] ? w6 : up_old.a[2][v];
+            g1 = cwl[v] ? w1 : lev.a[0][v];
+            g3 = cwr[v] ? w3 : lev.a[2][v];
+            g8 = cwl[v] ? w8 : a8;
+            g4 = a4;
+            g7 = cwr[v] ? w7 : a7;
+          } else {
+            g5 = (ub & 1u) ? w5 : up_old.a[0][v];
+            g2 = (ub & 2u) ? w2 : up_old.a[1][v];
+            g6 = (ub & 4u) ? w6 : up_old.a[2][v];
+            g1 = (lb & 1u) ? w1 : lev.a[0][v];
+            g3 = (lb & 4u) ? w3 : lev.a[2][v];
+            g8 = bit_l(v) ? w8 : a8;
+            g4 = ((sbits >> v) & 1u) ? w4 : a4;
+            g7 = bit_r(v) ? w7 : a7;
+          }
           const C g0 = lev.a[1][v];
-          const C g3 = (lb & 4u) ? w3 : lev.a[2][v];
-          const C g8 = bit_l(v) ? w8 : a8;
-          const C g4 = ((sbits >> v) & 1u) ? w4 : a4;
-          const C g7 = bit_r(v) ? w7 : a7;
           finish<C>(row_sum(g5, g2, g6), row_dif(g5, g6), row_sum(g1, g0, g3), row_dif(g1, g3),
                     row_sum(g8, g4, g7), row_dif(g8, g7), dn, jxn, jyn);
         } else {
@@ -269,7 +346,7 @@ __device__ __forceinline__ void strip_body(const StepArgs &a, const int chunk0, 
           jyn *= ej;
         }
         S e0 = T::enc(dn), e1 = T::enc(jxn), e2 = T::enc(jyn);
-        if (HASWALL && !((own_fluid >> v) & 1u)) {
+        if (HASWALL && !(COLF && kWordBlend) && !(COLF ? cfo[v] : ((own_fluid >> v) & 1u) != 0)) {
           e0 = own_raw[0].v[v];
           e1 = own_raw[1].v[v];
           e2 = own_raw[2].v[v];
@@ -277,6 +354,17 @@ __device__ __forceinline__ void strip_body(const StepArgs &a, const int chunk0, 
         out[0].v[v] = e0;
         out[1].v[v] = e1;
         out[2].v[v] = e2;
+      }
+      if constexpr (HASWALL && COLF && kWordBlend) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          uint32_t nw[kWords], ow[kWords];
+          __builtin_memcpy(nw, &out[q], sizeof(nw));
+          __builtin_memcpy(ow, &own_raw[q], sizeof(ow));
+#pragma unroll
+          for (int w = 0; w < kWords; ++w) nw[w] = (ow[w] & ckeep[w]) | (nw[w] & ~ckeep[w]);
+          __builtin_memcpy(&out[q], nw, sizeof(nw));
+        }
       }
       {
         // rows past ny and lanes past nx write to the trash area (no branch)
@@ -315,12 +403,14 @@ __device__ __forceinline__ void strip_body(const StepArgs &a, const int chunk0, 
       }
     }
     if constexpr (HASWALL) {
-      uint32_t sb = 0;
+      if constexpr (!COLF) {
+        uint32_t sb = 0;
 #pragma unroll
-      for (int v = 0; v < VEC; ++v)
-        sb |= (bit_l(v) | (((sbits >> v) & 1u) << 1) | (bit_r(v) << 2)) << (3 * v);
-      up_old.sb = sb;
-      lev.sb = sb;
+        for (int v = 0; v < VEC; ++v)
+          sb |= (bit_l(v) | (((sbits >> v) & 1u) << 1) | (bit_r(v) << 2)) << (3 * v);
+        up_old.sb = sb;
+        lev.sb = sb;
+      }
 #pragma unroll
       for (int v = 0; v < VEC; ++v) {
         own_d[v] = dd[v];
@@ -439,197 +529,5 @@ __global__ void __launch_bounds__(256) k_reduce_partial(ReduceArgs a) {
   }
 }
 
-
-}  // namespace lbt1
-
-namespace lbt1 {
-
-// ================================================================ batched step
-
-
-// Step arguments of a resident grid reading parity p.
-__device__ __forceinline__ StepArgs batch_step_args(const BatchGrid &g, const int p) {
-  StepArgs a;
-  for (int q = 0; q < 3; ++q) {
-    a.src[q] = g.plane[p][q];
-    a.dst[q] = g.plane[1 - p][q];
-  }
-  a.flags = g.flags;
-  a.nx = g.nx;
-  a.ny = g.ny;
-  a.pitch = g.pitch;
-  a.rs = g.rs;
-  a.periodic = g.periodic;
-  a.fx = g.fx;
-  a.fy = g.fy;
-  a.sc_d = g.sc_d;
-  a.sc_j = g.sc_j;
-  a.is_d = g.is_d;
-  a.is_j = g.is_j;
-  a.trash = g.trash;
-  a.sc_G = 0.0;
-  a.sc_rho0 = 1.0;
-  return a;
-}
-
-// True when every node the strip at (chunk0, y0) reads -- its NY rows, HALO rows
-// above and below, the 64 chunks of its lanes -- lies inside the grid and is a
-// FLUID node: no wall or fixed node, no row or column across an axis.  Such a strip
-// takes the wall-free body, which gives the same bits (the wall rule only ever
-// replaces arrivals from SOLID sources, and the sums run in the same order).
-// Wave-uniform: the flags of the footprint are OR-ed per lane, then voted.
-template <int VEC>
-__device__ __forceinline__ bool strip_interior(const StepArgs &a, const int chunk0, const int y0, const int NY,
-                                               const int HALO) {
-  if (chunk0 < 1 || (chunk0 + 63) * VEC > a.nx || y0 < HALO || y0 + NY + HALO > a.ny) return false;
-  const int lane = threadIdx.x & 63;
-  const uint8_t *f = a.flags + (long)(y0 - HALO) * a.pitch + (chunk0 - 1 + lane) * VEC;
-  uint32_t any = 0;
-  for (int i = 0; i < NY + 2 * HALO; ++i) {
-    const Pack<uint8_t, VEC> p = *reinterpret_cast<const Pack<uint8_t, VEC> *>(f + (long)i * a.pitch);
-#pragma unroll
-    for (int v = 0; v < VEC; ++v) any |= p.v[v];
-  }
-  return __ballot(any != 0) == 0;
-}
-
-// One wavefront per work item, grid-stride over all items of every grid with
-// columns per lane VEC.  Strips whose footprint holds walls, fixed nodes or an
-// edge of the grid take the wall-aware body, the others the wall-free one.
-template <int P, int VEC, int NY>
-__global__ void __launch_bounds__(256) k_step_batch(BatchStepArgs b) {
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int n = *b.count;
-  for (int it = blockIdx.x * 4 + wave; it < n; it += gridDim.x * 4) {
-    const int2 item = b.items[it];
-    const BatchGrid &g = b.grids[item.x];
-    if (b.step >= g.steps_left) continue;
-    const StepArgs a = batch_step_args(g, (g.parity0 + b.step) & 1);
-    const int sy = item.y / g.strips_x;   // along each row band, as in k_step_strip
-    const int sx = item.y - sy * g.strips_x;
-    // unit storage scales (the default; a wave-uniform test): the body without
-    // the scaling multiplications, which are exact no-ops then
-    const bool unit = !Traits<P>::kScaled || (g.sc_d == 1.0 && g.sc_j == 1.0 && g.is_d == 1.0 && g.is_j == 1.0);
-    if (strip_interior<VEC>(a, sx * 62, sy * NY, NY, 1)) {
-      if (unit)
-        strip_body<P, false, 0, VEC, NY, true>(a, sx * 62, sy * NY, lane);
-      else
-        strip_body<P, false, 0, VEC, NY, false>(a, sx * 62, sy * NY, lane);
-    } else if (g.wall == WALL_PAPER) {
-      if (!Traits<P>::kScaled || unit)
-        strip_body<P, true, WALL_PAPER, VEC, NY, true>(a, sx * 62, sy * NY, lane);
-      else
-        strip_body<P, true, WALL_PAPER, VEC, NY, false>(a, sx * 62, sy * NY, lane);
-    } else {
-      if (!Traits<P>::kScaled || unit)
-        strip_body<P, true, WALL_HALFWAY, VEC, NY, true>(a, sx * 62, sy * NY, lane);
-      else
-        strip_body<P, true, WALL_HALFWAY, VEC, NY, false>(a, sx * 62, sy * NY, lane);
-    }
-  }
-}
-
-
-template <int P>
-__global__ void __launch_bounds__(256) k_reduce_batch(BatchReduceArgs b) {
-  using T = Traits<P>;
-  using S = typename T::S;
-  const int n = *b.nitems;
-  __shared__ double part[4][6];
-  for (int it = blockIdx.x; it < n; it += gridDim.x) {
-    const int2 item = b.items[it];
-    const int slot = item.x;
-    const BatchGrid &g = b.grids[slot];
-    if (g.steps_left == 0) continue;  // not stepped in this burst (uniform in the block)
-    const int p = (g.parity0 + g.flips) & 1;
-    const S *c0 = static_cast<const S *>(g.plane[p][0]);
-    const S *c1 = static_cast<const S *>(g.plane[p][1]);
-    const S *c2 = static_cast<const S *>(g.plane[p][2]);
-    S *n0 = static_cast<S *>(b.snaps[slot * 3 + 0]);
-    S *n1 = static_cast<S *>(b.snaps[slot * 3 + 1]);
-    S *n2 = static_cast<S *>(b.snaps[slot * 3 + 2]);
-    double acc[6] = {0, 0, 0, 0, 0, 0};
-    const long nn = (long)g.nx * g.ny;
-    const long m0 = (long)item.y * kBatchReduceChunk;
-    const long m1 = min(nn, m0 + kBatchReduceChunk);
-    for (long m = m0 + threadIdx.x; m < m1; m += blockDim.x) {
-      const int y = (int)(m / g.nx);
-      const int x = (int)(m - (long)y * g.nx);
-      const long i = (long)y * g.rs + x;
-      if (g.flags[(long)y * g.pitch + x] != NODE_FLUID) continue;
-      const S r0 = c0[i], r1 = c1[i], r2 = c2[i];
-      const double d = (double)T::dec(r0) * g.sc_d;
-      const double jx = (double)T::dec(r1) * g.sc_j;
-      const double jy = (double)T::dec(r2) * g.sc_j;
-      acc[0] += d;
-      acc[1] += jx;
-      acc[2] += jy;
-      acc[4] += (__builtin_isfinite(d) && __builtin_isfinite(jx) && __builtin_isfinite(jy)) ? 0.0 : 1.0;
-      acc[5] += 1.0;
-      const double rho = 1.0 + d;
-      const double sr = 1.0 + (double)T::dec(n0[i]) * g.sc_d;
-      const double su = (double)T::dec(n1[i]) * g.sc_j / sr;
-      const double sv = (double)T::dec(n2[i]) * g.sc_j / sr;
-      acc[3] = __builtin_fmax(acc[3], __builtin_fmax(__builtin_fabs(jx / rho - su), __builtin_fabs(jy / rho - sv)));
-      n0[i] = r0;
-      n1[i] = r1;
-      n2[i] = r2;
-    }
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-#pragma unroll
-      for (int q = 0; q < 6; ++q) {
-        const double o = __shfl_xor(acc[q], off);
-        acc[q] = q == 3 ? __builtin_fmax(acc[q], o) : acc[q] + o;
-      }
-    }
-    const int wave = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) {
-#pragma unroll
-      for (int q = 0; q < 6; ++q) part[wave][q] = acc[q];
-    }
-    __syncthreads();
-    if (threadIdx.x < 6) {
-      const int q = threadIdx.x;
-      double v = part[0][q];
-      for (int w = 1; w < (int)(blockDim.x >> 6); ++w) v = q == 3 ? __builtin_fmax(v, part[w][q]) : v + part[w][q];
-      b.partials[(long)it * 6 + q] = v;
-    }
-    __syncthreads();
-  }
-}
-
-// The partials of each active grid (fixed order: lane-strided, then a butterfly)
-// into out[slot * 6 + q].
-__global__ void __launch_bounds__(64) k_reduce_batch_final(BatchReduceArgs b) {
-  const int n = *b.nactive;
-  for (int k = blockIdx.x; k < n; k += gridDim.x) {
-    const int slot = b.active[k];
-    const int2 r = b.ranges[slot];
-    // lane l: partial rows l, l + 64, ... of the grid in order, then a fixed butterfly
-    const int l = threadIdx.x;
-    double acc[6] = {0, 0, 0, 0, 0, 0};
-    for (int i = l; i < r.y; i += 64) {
-#pragma unroll
-      for (int q = 0; q < 6; ++q) {
-        const double x = b.partials[(long)(r.x + i) * 6 + q];
-        acc[q] = q == 3 ? __builtin_fmax(acc[q], x) : acc[q] + x;
-      }
-    }
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-#pragma unroll
-      for (int q = 0; q < 6; ++q) {
-        const double o = __shfl_xor(acc[q], off);
-        acc[q] = q == 3 ? __builtin_fmax(acc[q], o) : acc[q] + o;
-      }
-    }
-    if (l == 0) {
-#pragma unroll
-      for (int q = 0; q < 6; ++q) b.out[slot * 6 + q] = acc[q];
-    }
-  }
-}
 
 }  // namespace lbt1

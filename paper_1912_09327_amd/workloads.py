@@ -35,7 +35,7 @@ def run_cavities(n, cap, tol, torch, log, burst=100, seed=4, tune=True, shape=No
     """The uneven-cavity population (n cavities, seed 4) run batched and one grid at a
     time, each grid to residual <= tol (tol < 0: never) or cap steps.  The batch's tile
     shape is the autotuner's (tune; its time is not counted), or `shape`
-    (fuse, rows), else the heuristic.  Returns the record: MLUPS of both forms, stop
+    (fuse, rows, lds, vec_cap), else the heuristic.  Returns the record: MLUPS of both forms, stop
     reasons, the alone-vs-mix identity on a sample of final fields, and the FP16
     storage error against FP64 runs of the same steps."""
     from . import _capi as C
@@ -129,8 +129,9 @@ def bench_cavities(args, torch, log):
     cap, tol = args.max_steps, 1e-8
     shape = None
     if getattr(args, "batch_shape", None):
-        f, *rows = [int(v) for v in args.batch_shape.split(":")]
-        shape = (f, rows)
+        f, *rest = [int(v) for v in args.batch_shape.split(":")]
+        rows, extra = rest[:5], rest[5:]
+        shape = (f, rows, extra[0] if extra else 0, extra[1] if len(extra) > 1 else 0)
     r = run_cavities(args.cavities, cap, tol, torch, log, tune=not args.no_tune, shape=shape,
                      plain=not getattr(args, "batched_only", False))
     return {

@@ -129,14 +129,20 @@ def test_3d_errors():
 @pytest.mark.parametrize("q", [19, 27])
 @pytest.mark.parametrize("prec", ["f64", "f32", "f16s"])
 @pytest.mark.parametrize("shape", [(9, 21, 70), (16, 4, 64), (20, 7, 130), (1, 3, 5)])
-def test_3d_tile_bitwise_equals_gather(shape, prec, q):
+@pytest.mark.parametrize("kind,wall", [("periodic", "paper"), ("box", "paper"), ("box", "halfway"),
+                                       ("plates", "paper"), ("plates", "halfway"), ("open", "halfway")])
+def test_3d_tile_bitwise_equals_gather(kind, wall, shape, prec, q):
+    """The tile kernel, with walls, fixed nodes and non-periodic axes as well, gives the
+    bits of one thread per node."""
     from paper_1912_09327_amd.grid3d import Grid3D
-    flags, rho, js, per = _case("periodic", shape, 7)
+    if kind == "box" and min(shape) < 3:
+        pytest.skip("a box needs three nodes along every axis")
+    flags, rho, js, per = _case(kind, shape, 7)
     nz, ny, nx = shape
     F = (1e-5, 2e-6, -3e-6)
     out = {}
     for kern in ("gather", "tile"):
-        g = Grid3D(nx, ny, nz, q=q, prec=prec, periodic=per, force=F)
+        g = Grid3D(nx, ny, nz, q=q, prec=prec, wall=wall, periodic=per, force=F)
         try:
             g.set_kernel(kern)
             g.set_geometry(flags, rho, *js)
@@ -149,17 +155,15 @@ def test_3d_tile_bitwise_equals_gather(shape, prec, q):
         assert np.array_equal(a, b)
 
 
-def test_3d_tile_refused_with_walls():
-    from paper_1912_09327_amd import _capi as C
+def test_3d_tile_is_the_default_with_walls():
     from paper_1912_09327_amd.grid3d import Grid3D
     flags, rho, js, per = _case("plates", (8, 8, 64), 8)
     g = Grid3D(64, 8, 8, q=19, periodic=per)
     try:
         g.set_geometry(flags, rho, *js)
+        assert g.kernel() == "tile"
+        g.set_kernel("gather")
         assert g.kernel() == "gather"
-        with pytest.raises(C.Lbt1Error) as e:
-            g.set_kernel("tile")
-        assert e.value.status == C.EINVAL
         g.step(2)
     finally:
         g.close()

@@ -30,10 +30,13 @@ def _grid(spec, prec):
 
 
 # odd widths 147 and 261 are not periodic in x: their strips take 2 and 4 columns
-# per lane with the last chunk of a row running into the (SOLID) row padding
+# per lane with the last chunk of a row running into the (SOLID) row padding.  In
+# the four-column class 256 is one strip wide, 517 three strips (the last of three
+# chunks) and 362 two.
 SPECS = [("cavity", 37, 0.08), ("cavity", 64, 0.05), ("channel", 96, 0.8), ("cavity", 130, 0.1),
-         ("channel", 200, 0.7), ("cavity", 256, 0.03), ("cavity", 147, 0.07), ("cavity", 261, 0.05)]
-BUDGETS = [130, 250, 75, 300, 260, 190, 121, 97]
+         ("channel", 200, 0.7), ("cavity", 256, 0.03), ("cavity", 147, 0.07), ("cavity", 261, 0.05),
+         ("cavity", 362, 0.04), ("cavity", 517, 0.02)]
+BUDGETS = [130, 250, 75, 300, 260, 190, 121, 97, 101, 66]
 
 
 @pytest.mark.parametrize("prec", ["f32", "f16s", "bf16s"])
@@ -115,7 +118,8 @@ def _run_mix_and_compare(prec, shape=None, burst=40, tune=False):
 # tile shapes: fuse mode, strip heights of the five classes (one step at 1, 2, 4
 # columns per lane; two steps at 2; resident in LDS) and LDS residency of small grids
 SHAPES = [(1, (6, 6, 6, 2, 0), 0), (1, (14, 14, 14, 6, 0), 0), (2, (6, 14, 6, 14, 0), 0), (1, (0, 0, 0, 30, 0), 0),
-          (0, (14, 6, 14, 0, 0), 0), (0, (0, 0, 0, 0, 6), 1), (1, (6, 6, 6, 14, 14), 1)]
+          (0, (14, 6, 14, 0, 0), 0), (0, (0, 0, 0, 0, 6), 1), (1, (6, 6, 6, 14, 14), 1), (0, (6, 14, 6, 0, 0), 0),
+          (2, (14, 14, 14, 6, 0), 0), (0, (14, 14, 14, 0, 0), 0, 2), (2, (6, 6, 6, 30, 0), 0, 1)]
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32", "f16s", "bf16s"])
@@ -134,6 +138,7 @@ def test_batch_autotune_keeps_state_and_bits(prec):
     it the batch still ends every grid where the grid alone ends."""
     shape = _run_mix_and_compare(prec, None, burst=40, tune=True)
     assert shape["fuse"] in (0, 1, 2) and shape["lds"] in (0, 1) and len(shape["rows"]) == 5
+    assert shape["vec_cap"] in (1, 2, 4)
 
 
 def test_batch_shape_refusals():
@@ -142,7 +147,7 @@ def test_batch_shape_refusals():
     b = Batch(1 << 28, 4)
     try:
         for bad in ((3, (0, 0, 0, 0)), (0, (7, 0, 0, 0)), (1, (0, 0, 0, 22)), (0, (0, 0, 0, 0, 22)),
-                    (0, (0, 0, 0, 0), 2)):
+                    (0, (0, 0, 0, 0), 2), (0, (0, 0, 0, 0), 0, 3)):
             with pytest.raises(C.Lbt1Error) as e:
                 b.set_shape(*bad)
             assert e.value.status == C.EINVAL

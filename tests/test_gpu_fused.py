@@ -166,3 +166,27 @@ def test_autotune_leaves_the_state_and_the_trajectory_unchanged(prec, kind):
     assert not all(np.array_equal(a, b) for a, b in zip(before, mid))
     for a, b in zip(ref, got):
         assert np.array_equal(a, b), cfg
+
+
+def test_tuned_shape_of_a_walled_grid_is_not_reused_on_a_periodic_one():
+    """The autotuner's choice is remembered per grid kind.  A walled grid of odd width
+    may tune to strips whose chunks do not divide the width (its last chunk is padded
+    with solid columns); a channel of the same size, precision and wall rule that is
+    periodic in x cannot take that shape.  The channel must bind its own default shape
+    and match the oracle."""
+    from paper_1912_09327_amd.grid import Grid
+    L = 263
+    flags, rho, jx, jy, per = I.cavity(L, 0.05)
+    g = Grid(L, L, prec="f64", periodic=per)
+    try:
+        g.set_geometry(flags, rho, jx, jy)
+        cfg, _ = g.autotune(steps=12, reps=2)
+    finally:
+        g.close()
+    cflags, cper = I.channel(L, L)
+    crho, cjx, cjy = _state(L, L, 17)
+    F = (2e-6, 0.0)
+    got = gpu_run(cflags, crho, cjx, cjy, 20, "f64", "paper", cper, F)
+    ref = oracle_run(cflags, crho, cjx, cjy, 20, "paper", cper, F)
+    ex, ej = field_errors(got, ref, cflags)
+    assert ex <= TOL["f64"] and ej <= JTOL["f64"], (cfg, ex, ej)

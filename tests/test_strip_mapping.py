@@ -250,7 +250,8 @@ def test_batch_item_lists_in_bounds_and_write_once(c):
                     nch = -(-g["nx"] // cls)
                     sx = (nch + 61) // 62
                     sy = (g["ny"] + rows - 1) // rows
-                    items += [(slot, k) for k in range(sx * sy)]
+                    # (slot, 4 * strip + kind), any kind
+                    items += [(slot, (k << 2) | (k % 3)) for k in range(sx * sy)]
                 visited = []
                 for b in range(blocks):
                     for wave in range(4):
@@ -259,7 +260,8 @@ def test_batch_item_lists_in_bounds_and_write_once(c):
                             visited.append(items[it])
                             it += blocks * 4
                 assert sorted(visited) == sorted(items)
-                for slot, k in visited:
+                for slot, y in visited:
+                    k = y >> 2
                     g = grids[slot]
                     nch = -(-g["nx"] // cls)
                     strips_x = (nch + 61) // 62
@@ -271,3 +273,87 @@ def test_batch_item_lists_in_bounds_and_write_once(c):
                 assert len(g["written"]) == 3 * g["ny"] * nch
                 assert set(g["written"].values()) == {1}
                 g["written"] = {}
+
+
+def strip_interior(flags, per, VEC, chunk0, y0, NY, HALO):
+    """Model of strip_interior: the stored chunks widened by HALO columns and the
+    strip's rows widened by HALO rows, all inside the grid and FLUID."""
+    ny, nx = flags.shape
+    nch = -(-nx // VEC)
+    ce = min(nch, chunk0 + 62)
+    if chunk0 < 1 or ce <= chunk0 or ce * VEC + HALO > nx or y0 < HALO or y0 + NY + HALO > ny:
+        return False
+    any_ = 0
+    for lane in range(64):
+        ch = chunk0 - 1 + lane
+        lo = VEC - HALO if ch == chunk0 - 1 else 0
+        hi = HALO if ch == ce else (VEC if ch < ce else 0)
+        for i in range(NY + 2 * HALO):
+            for v in range(lo, hi):
+                any_ |= int(flags[y0 - HALO + i, ch * VEC + v])   # inside: ch * VEC + v < nx
+    return any_ == 0
+
+
+def strip_colwall(flags, per, VEC, chunk0, y0, NY, HALO):
+    """Model of strip_colwall: the flags of the 64 lanes' chunks, as the wall-aware
+    body loads them, equal in every footprint row of each column."""
+    ny, nx = flags.shape
+    px, py = bool(per & 1), bool(per & 2)
+    if not py and (y0 < HALO or y0 + NY + HALO > ny):
+        return False
+    padded = np.full((ny, -(-nx // VEC) * VEC), 1, np.uint8)   # row padding is SOLID
+    padded[:, :nx] = flags
+    nch = padded.shape[1] // VEC
+    for lane in range(64):
+        ch = chunk0 - 1 + lane
+        if ch < 0 or ch >= nch:
+            if not px:
+                continue
+            ch %= nch
+        rows = [int(wrap_axis(y0 - HALO + i, ny, py)) for i in range(NY + 2 * HALO)]
+        cols = padded[rows, ch * VEC:(ch + 1) * VEC]
+        if (cols != cols[0]).any():
+            return False
+    return True
+
+
+@pytest.mark.parametrize("VEC,HALO", [(1, 1), (2, 1), (4, 1), (2, 2)])
+def test_strip_kinds_hold_what_their_bodies_assume(VEC, HALO):
+    """Brute force over cavities, channels and obstacle fields: a strip classed
+    interior has every node within HALO of a stored node inside the grid and FLUID;
+    a strip classed column-walls sees the same flags in every row of each column."""
+    from paper_1912_09327_amd import inputs as I
+    rng = np.random.default_rng(11)
+    geos = []
+    for L in (37, 70, 130, 261, 300):
+        f = I.cavity(L, 0.05)[0]
+        geos.append((f, 0))
+        ch, per = I.channel(L, L // 2 + 3)
+        geos.append((ch, per))
+    geos.append((I.cavity(600, 0.05, ny=40)[0], 0))
+    geos.append(I.channel(600, 40))
+    f = np.zeros((50, 140), np.uint8)
+    f[rng.random(f.shape) < 0.02] = I.SOLID
+    geos += [(f, 3), (f, 0)]
+    seen = {"interior": 0, "colwall": 0}
+    for flags, per in geos:
+        ny, nx = flags.shape
+        nch = -(-nx // VEC)
+        for NY in (2, 6, 14):
+            for sy in range(-(-ny // NY)):
+                for sx in range(-(-nch // 62)):
+                    c0, y0 = sx * 62, sy * NY
+                    if strip_interior(flags, per, VEC, c0, y0, NY, HALO):
+                        seen["interior"] += 1
+                        ce = min(nch, c0 + 62)
+                        xs = [x for x in range(c0 * VEC, ce * VEC) if x < nx]
+                        ys = [y for y in range(y0, min(y0 + NY, ny))]
+                        for y in ys:
+                            for x in xs:
+                                for dy in range(-HALO, HALO + 1):
+                                    for dx in range(-HALO, HALO + 1):
+                                        assert 0 <= y + dy < ny and 0 <= x + dx < nx
+                                        assert flags[y + dy, x + dx] == I.FLUID
+                    elif strip_colwall(flags, per, VEC, c0, y0, NY, HALO):
+                        seen["colwall"] += 1
+    assert seen["interior"] > 0 and seen["colwall"] > 0
