@@ -186,10 +186,10 @@ def copy_ceiling(nbytes=2 << 30):
 
 # Vector-ALU issue ceiling: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (one wave64 VALU
 # instruction per SIMD every 4 cycles), in T lane-operations/s.  Operations per update
-# in the kernel expression: emission 32 and target sums 14; the 16-bit storage codec
+# in the kernel expression: emission 29 and target sums 14; the 16-bit storage codec
 # adds about 12.
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
-ALG_OPS_PER_LUP = {"f64": 46, "f32": 46, "f16s": 58, "bf16s": 58}
+ALG_OPS_PER_LUP = {"f64": 43, "f32": 43, "f16s": 55, "bf16s": 55}
 
 
 def kernel_source_hash():

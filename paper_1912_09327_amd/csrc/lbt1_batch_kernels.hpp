@@ -133,7 +133,7 @@ __global__ void __launch_bounds__(256) k_batch_classify(BatchClassifyArgs b) {
 // interior strips, the wall-aware body with the flags of one row where walls run
 // down whole columns, else the general wall-aware body.  All give the bits of the
 // single-grid kernels.
-template <int P, int VEC, int NY>
+template <int P, int VEC, int NY, int PF>
 __device__ __forceinline__ void batch_strip(const BatchGrid &g, const StepArgs &a, const int kind, const int c0,
                                             const int y0, const int lane) {
   // unit storage scales (the default; a wave-uniform test): the bodies without
@@ -141,33 +141,39 @@ __device__ __forceinline__ void batch_strip(const BatchGrid &g, const StepArgs &
   const bool unit = !Traits<P>::kScaled || (g.sc_d == 1.0 && g.sc_j == 1.0 && g.is_d == 1.0 && g.is_j == 1.0);
   if (kind == STRIP_INTERIOR) {
     if (unit)
-      strip_body<P, false, 0, VEC, NY, true>(a, c0, y0, lane);
+      strip_body<P, false, 0, VEC, NY, true, false, PF>(a, c0, y0, lane);
     else
-      strip_body<P, false, 0, VEC, NY, false>(a, c0, y0, lane);
+      strip_body<P, false, 0, VEC, NY, false, false, PF>(a, c0, y0, lane);
   } else if (kind == STRIP_COLUMN_WALLS) {
     if (g.wall == WALL_PAPER) {
       if (unit)
-        strip_body<P, true, WALL_PAPER, VEC, NY, true, true>(a, c0, y0, lane);
+        strip_body<P, true, WALL_PAPER, VEC, NY, true, true, PF>(a, c0, y0, lane);
       else
-        strip_body<P, true, WALL_PAPER, VEC, NY, false, true>(a, c0, y0, lane);
+        strip_body<P, true, WALL_PAPER, VEC, NY, false, true, PF>(a, c0, y0, lane);
     } else {
       if (unit)
-        strip_body<P, true, WALL_HALFWAY, VEC, NY, true, true>(a, c0, y0, lane);
+        strip_body<P, true, WALL_HALFWAY, VEC, NY, true, true, PF>(a, c0, y0, lane);
       else
-        strip_body<P, true, WALL_HALFWAY, VEC, NY, false, true>(a, c0, y0, lane);
+        strip_body<P, true, WALL_HALFWAY, VEC, NY, false, true, PF>(a, c0, y0, lane);
     }
   } else if (g.wall == WALL_PAPER) {
     if (unit)
-      strip_body<P, true, WALL_PAPER, VEC, NY, true>(a, c0, y0, lane);
+      strip_body<P, true, WALL_PAPER, VEC, NY, true, false, PF>(a, c0, y0, lane);
     else
-      strip_body<P, true, WALL_PAPER, VEC, NY, false>(a, c0, y0, lane);
+      strip_body<P, true, WALL_PAPER, VEC, NY, false, false, PF>(a, c0, y0, lane);
   } else {
     if (unit)
-      strip_body<P, true, WALL_HALFWAY, VEC, NY, true>(a, c0, y0, lane);
+      strip_body<P, true, WALL_HALFWAY, VEC, NY, true, false, PF>(a, c0, y0, lane);
     else
-      strip_body<P, true, WALL_HALFWAY, VEC, NY, false>(a, c0, y0, lane);
+      strip_body<P, true, WALL_HALFWAY, VEC, NY, false, false, PF>(a, c0, y0, lane);
   }
 }
+
+// Rows in flight ahead of the row being computed in the batched strips (one-step
+// and two-step walled bodies): deeper than the single-grid kernels' (two), since a
+// wavefront of the batch spends much of its time waiting for its rows and the
+// registers allow it at two wavefronts per SIMD (six rows spill scalar registers).
+constexpr int kBatchPrefetch = 4;
 
 // One wavefront per work item, grid-stride over all items of every grid with
 // columns per lane VEC.
@@ -186,7 +192,7 @@ __global__ void __launch_bounds__(256) k_step_batch(BatchStepArgs b) {
     const int strip = item.y >> 2;
     const int sy = strip / g.strips_x;   // along each row band, as in k_step_strip
     const int sx = strip - sy * g.strips_x;
-    batch_strip<P, VEC, NY>(g, a, item.y & 3, sx * 62, sy * NY, lane);
+    batch_strip<P, VEC, NY, kBatchPrefetch>(g, a, item.y & 3, sx * 62, sy * NY, lane);
   }
 }
 
@@ -302,6 +308,8 @@ namespace lbt1 {
 // step in the single-step body of the same strip shape.
 template <int P, int NY>
 __global__ void __launch_bounds__(256) k_step_batch_fused(BatchStepArgs b) {
+  // (FP64 keeps the single-grid depth: four rows of 8-byte values would spill)
+  constexpr int kPF = P == P_F64 ? kPrefetch : kBatchPrefetch;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // (see k_step_batch)
   const int n = *b.count;
@@ -327,14 +335,14 @@ __global__ void __launch_bounds__(256) k_step_batch_fused(BatchStepArgs b) {
     } else if (left >= 2) {
       if (g.wall == WALL_PAPER) {
         if (unit)
-          fused_wall_body<P, WALL_PAPER, 2, NY, true>(a, sx * 62, sy * NY, lane);
+          fused_wall_body<P, WALL_PAPER, 2, NY, true, kPF>(a, sx * 62, sy * NY, lane);
         else
-          fused_wall_body<P, WALL_PAPER, 2, NY, false>(a, sx * 62, sy * NY, lane);
+          fused_wall_body<P, WALL_PAPER, 2, NY, false, kPF>(a, sx * 62, sy * NY, lane);
       } else {
         if (unit)
-          fused_wall_body<P, WALL_HALFWAY, 2, NY, true>(a, sx * 62, sy * NY, lane);
+          fused_wall_body<P, WALL_HALFWAY, 2, NY, true, kPF>(a, sx * 62, sy * NY, lane);
         else
-          fused_wall_body<P, WALL_HALFWAY, 2, NY, false>(a, sx * 62, sy * NY, lane);
+          fused_wall_body<P, WALL_HALFWAY, 2, NY, false, kPF>(a, sx * 62, sy * NY, lane);
       }
     } else {
       if (g.wall == WALL_PAPER) {

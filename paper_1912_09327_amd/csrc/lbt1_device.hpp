@@ -88,16 +88,20 @@ __device__ __forceinline__ void emit(C d, C jx, C jy, C Fx, C Fy, C f[9]) {
   const C pyy = Jy * uy;
   const C pxy = Jx * uy;
   const C t = pxx + pyy;
-  f[0] = C(4.0 / 9.0) * fmaC<C>(C(-1.5), t, d);
-  // axes: w = 1/9, bracket d + 3 P_aa - 1.5 P_bb +- 3 J_a
-  const C bx = C(1.0 / 9.0) * fmaC<C>(C(3), pxx, fmaC<C>(C(-1.5), pyy, d));
-  const C by = C(1.0 / 9.0) * fmaC<C>(C(3), pyy, fmaC<C>(C(-1.5), pxx, d));
+  // every bracket holds base = d - 1.5 tr P: the rest link's is base itself
+  const C base = fmaC<C>(C(-1.5), t, d);
+  f[0] = C(4.0 / 9.0) * base;
+  const C b9 = C(1.0 / 9.0) * base;
+  // axes: w = 1/9, bracket base + 4.5 P_aa +- 3 J_a
+  const C bx = fmaC<C>(C(0.5), pxx, b9);
+  const C by = fmaC<C>(C(0.5), pyy, b9);
   f[1] = fmaC<C>(C(1.0 / 3.0), Jx, bx);
   f[3] = fmaC<C>(C(-1.0 / 3.0), Jx, bx);
   f[2] = fmaC<C>(C(1.0 / 3.0), Jy, by);
   f[4] = fmaC<C>(C(-1.0 / 3.0), Jy, by);
-  // diagonals: w = 1/36, bracket d + 3 tr P +- 9 P_xy + 3 e.J
-  const C bd = C(1.0 / 36.0) * fmaC<C>(C(3), t, d);
+  // diagonals: w = 1/36, bracket base + 4.5 tr P +- 9 P_xy + 3 e.J (base / 36 is
+  // b9 / 4, exact)
+  const C bd = fmaC<C>(C(0.125), t, C(0.25) * b9);
   const C bp = fmaC<C>(C(0.25), pxy, bd);
   const C bm = fmaC<C>(C(-0.25), pxy, bd);
   const C sp = Jx + Jy;

@@ -148,8 +148,9 @@ __device__ __forceinline__ void wall_feed(WallStage<P, WALL, VEC> &st, const boo
 }
 
 // UNIT: both storage scales are 1 (the default), so the codec's scaling
-// multiplications are exact no-ops and are left out.
-template <int P, int WALL, int VEC, int NY, bool UNIT>
+// multiplications are exact no-ops and are left out.  PF: source rows whose loads
+// are in flight ahead of the row being fed.
+template <int P, int WALL, int VEC, int NY, bool UNIT, int PF = kPrefetch>
 __device__ __forceinline__ void fused_wall_body(const StepArgs &a, const int chunk0, const int y0, const int lane) {
   using T = Traits<P>;
   using C = typename T::C;
@@ -216,7 +217,6 @@ __device__ __forceinline__ void fused_wall_body(const StepArgs &a, const int chu
   };
 
   WallStage<P, WALL, VEC> stage[2] = {};
-  constexpr int PF = kPrefetch;
   constexpr int NR = NY + 4;
   Row ring[PF + 1];
 #pragma unroll

@@ -115,7 +115,8 @@ constexpr int kPrefetch = 2;
 // arrivals from the node's own column (straight up and down) are never from a wall
 // when the node is FLUID, so only the six arrivals from the neighbouring columns go
 // through a select.  Same values summed in the same order: same bits.
-template <int P, bool HASWALL, int WALL, int VEC, int NY, bool UNIT = false, bool COLF = false>
+// PF: rows whose loads are in flight ahead of the row being computed.
+template <int P, bool HASWALL, int WALL, int VEC, int NY, bool UNIT = false, bool COLF = false, int PF = kPrefetch>
 __device__ __forceinline__ void strip_body(const StepArgs &a, const int chunk0, const int y0,
                                            const int lane) {
   using T = Traits<P>;
@@ -427,7 +428,6 @@ __device__ __forceinline__ void strip_body(const StepArgs &a, const int chunk0, 
   };
 
   // Fully unrolled so that every ring slot and up-buffer role is static.
-  constexpr int PF = kPrefetch;
   Row ring[PF + 1];
 #pragma unroll
   for (int i = 0; i < PF; ++i) load_row(i, ring[i]);

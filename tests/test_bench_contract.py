@@ -31,7 +31,7 @@ def test_roofline_peaks():
     assert b.HBM_PEAK_GBPS == 8000.0
     # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
     assert b.VALU_PEAK_TOPS == pytest.approx(39.3216)
-    assert b.ALG_OPS_PER_LUP["f32"] == 32 + 14
+    assert b.ALG_OPS_PER_LUP["f32"] == 29 + 14
     assert b.ALG_OPS_PER_LUP["f16s"] > b.ALG_OPS_PER_LUP["f32"]
 
 
