@@ -346,9 +346,11 @@ lbt1_status lbt1_grid3d_step(lbt1_grid3d *g, int64_t n) {
   hipError_t e;
   if ((e = hipSetDevice(g->device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
   const dim3 block = g->tile ? dim3(64 * kTile3Y, 1, 1) : dim3(64, 4, 1);
-  const dim3 grid = g->tile ? dim3((g->nx + kTile3X - 1) / kTile3X, (g->ny + kTile3Y - 1) / kTile3Y,
-                                   (g->nz + zchunk_for(g->prec) - 1) / zchunk_for(g->prec))
-                            : dim3((g->nx + 63) / 64, (g->ny + 3) / 4, g->nz);
+  // tile kernel: one block per tile, rounded up to a multiple of the 8 XCDs (the
+  // kernel maps block b to a tile of XCD b % 8's contiguous range)
+  const long ntiles = (long)((g->nx + kTile3X - 1) / kTile3X) * ((g->ny + kTile3Y - 1) / kTile3Y) *
+                      ((g->nz + zchunk_for(g->prec) - 1) / zchunk_for(g->prec));
+  const dim3 grid = g->tile ? dim3((unsigned)((ntiles + 7) / 8 * 8), 1, 1) : dim3((g->nx + 63) / 64, (g->ny + 3) / 4, g->nz);
   for (int64_t s = 0; s < n; ++s) {
     Step3Args a = step3_args(g, g->parity);
     void *args[] = {&a};

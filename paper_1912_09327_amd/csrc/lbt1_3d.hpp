@@ -212,7 +212,17 @@ __global__ void __launch_bounds__(64 * TY) k_step3_tile(Step3Args a) {
   __shared__ uint8_t sF[HASWALL ? 3 : 1][HASWALL ? HN : 1];  // flags (SOLID outside a non-periodic axis)
   const int tid = threadIdx.x;
   const int tx = tid & 63, ty = tid >> 6;
-  const int x0 = blockIdx.x * kTile3X, y0 = blockIdx.y * TY, z0 = blockIdx.z * ZC;
+  // A one-dimensional launch of 8 * per blocks (lbt1_grid3d_step): block b runs on XCD
+  // b % 8, and XCD x takes the tiles [x * per, (x + 1) * per) in x-fastest order, so
+  // the tiles whose halo columns and rows a tile shares are mostly on its own XCD
+  // and its L2 (2-3 % faster at 512^3 than a three-dimensional grid, whose
+  // consecutive blocks, the x neighbours, go to different XCDs).
+  const int ntx = (a.nx + kTile3X - 1) / kTile3X, nty = (a.ny + TY - 1) / TY, ntz = (a.nz + ZC - 1) / ZC;
+  const int ntiles = ntx * nty * ntz, per = (ntiles + 7) / 8;
+  const int tile = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+  if (tile >= ntiles) return;  // uniform across the block
+  const int tz = tile / (ntx * nty), trow = tile - tz * ntx * nty, tyi = trow / ntx, txi = trow - tyi * ntx;
+  const int x0 = txi * kTile3X, y0 = tyi * TY, z0 = tz * ZC;
   const C Fx = C(a.fx), Fy = C(a.fy), Fz = C(a.fz);
   const bool px = !HASWALL || (a.periodic & 1u), py = !HASWALL || (a.periodic & 2u),
              pz = !HASWALL || (a.periodic & 4u);

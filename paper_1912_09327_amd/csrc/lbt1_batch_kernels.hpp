@@ -169,10 +169,11 @@ __device__ __forceinline__ void batch_strip(const BatchGrid &g, const StepArgs &
   }
 }
 
-// Rows in flight ahead of the row being computed in the batched strips (one-step
-// and two-step walled bodies): deeper than the single-grid kernels' (two), since a
-// wavefront of the batch spends much of its time waiting for its rows and the
-// registers allow it at two wavefronts per SIMD (six rows spill scalar registers).
+// Rows in flight ahead of the row being computed in the one-step batched strips:
+// deeper than the single-grid kernels' (two), since a wavefront of the batch
+// spends much of its time waiting for its rows and the registers allow it at two
+// wavefronts per SIMD (six rows spill scalar registers).  (The two-step walled
+// body keeps two: four gave the same batch time.)
 constexpr int kBatchPrefetch = 4;
 
 // One wavefront per work item, grid-stride over all items of every grid with
@@ -308,8 +309,6 @@ namespace lbt1 {
 // step in the single-step body of the same strip shape.
 template <int P, int NY>
 __global__ void __launch_bounds__(256) k_step_batch_fused(BatchStepArgs b) {
-  // (FP64 keeps the single-grid depth: four rows of 8-byte values would spill)
-  constexpr int kPF = P == P_F64 ? kPrefetch : kBatchPrefetch;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // (see k_step_batch)
   const int n = *b.count;
@@ -335,14 +334,14 @@ __global__ void __launch_bounds__(256) k_step_batch_fused(BatchStepArgs b) {
     } else if (left >= 2) {
       if (g.wall == WALL_PAPER) {
         if (unit)
-          fused_wall_body<P, WALL_PAPER, 2, NY, true, kPF>(a, sx * 62, sy * NY, lane);
+          fused_wall_body<P, WALL_PAPER, 2, NY, true>(a, sx * 62, sy * NY, lane);
         else
-          fused_wall_body<P, WALL_PAPER, 2, NY, false, kPF>(a, sx * 62, sy * NY, lane);
+          fused_wall_body<P, WALL_PAPER, 2, NY, false>(a, sx * 62, sy * NY, lane);
       } else {
         if (unit)
-          fused_wall_body<P, WALL_HALFWAY, 2, NY, true, kPF>(a, sx * 62, sy * NY, lane);
+          fused_wall_body<P, WALL_HALFWAY, 2, NY, true>(a, sx * 62, sy * NY, lane);
         else
-          fused_wall_body<P, WALL_HALFWAY, 2, NY, false, kPF>(a, sx * 62, sy * NY, lane);
+          fused_wall_body<P, WALL_HALFWAY, 2, NY, false>(a, sx * 62, sy * NY, lane);
       }
     } else {
       if (g.wall == WALL_PAPER) {
