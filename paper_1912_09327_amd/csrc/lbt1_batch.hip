@@ -9,7 +9,10 @@
 // grid joins and each class's strip height are the batch's tile shape: a
 // heuristic by default (6-row strips for classes too short to give every CU
 // several wavefronts, since a strip walks its rows one after another), or what
-// lbt1_batch_autotune measured fastest on the resident grids.  A burst of K steps
+// lbt1_batch_autotune measured fastest on the resident grids.  Each strip's kind
+// (interior, walls down whole columns, general), which picks the body it runs,
+// is found once per work list on the device (k_batch_classify) and kept in its
+// work item.  A burst of K steps
 // plus the per-grid residual check is one HIP graph with one chain of launches
 // per class (the classes touch disjoint grids, so their chains run side by side);
 // the grid descriptors and work lists live in device memory, so admitting or
