@@ -38,74 +38,6 @@ __device__ __forceinline__ StepArgs batch_step_args(const BatchGrid &g, const in
   return a;
 }
 
-// True when every node whose emissions reach a stored node of the strip at
-// (chunk0, y0) through HALO steps is a FLUID node inside the grid: the stored
-// chunks [chunk0, min(nch, chunk0 + 62)) widened by HALO columns on either side
-// and its NY rows widened by HALO rows above and below, with no row or column
-// across an axis.  Such a strip takes the wall-free body, which gives the same bits
-// (the wall rule only ever replaces arrivals from SOLID sources, and the sums run
-// in the same order).  The halo lanes' other columns feed only nodes that are not
-// stored.  HALO <= VEC.  Wave-uniform: the flags are OR-ed per lane, then voted.
-template <int VEC>
-__device__ __forceinline__ bool strip_interior(const StepArgs &a, const int chunk0, const int y0, const int NY,
-                                               const int HALO) {
-  const int nch = (a.nx + VEC - 1) / VEC;
-  const int ce = min(nch, chunk0 + 62);
-  if (chunk0 < 1 || ce <= chunk0 || ce * VEC + HALO > a.nx || y0 < HALO || y0 + NY + HALO > a.ny) return false;
-  const int lane = threadIdx.x & 63;
-  const int ch = chunk0 - 1 + lane;
-  // columns [lo, hi) of this lane's chunk that the stored nodes draw on
-  const int lo = ch == chunk0 - 1 ? VEC - HALO : 0;
-  const int hi = ch == ce ? HALO : (ch < ce ? VEC : 0);
-  uint32_t any = 0;
-  if (hi > lo) {
-    // ch <= ce and ce * VEC < nx, so the pack lies inside the row's pitch
-    const uint8_t *f = a.flags + (long)(y0 - HALO) * a.pitch + (long)ch * VEC;
-    for (int i = 0; i < NY + 2 * HALO; ++i) {
-      const Pack<uint8_t, VEC> p = *reinterpret_cast<const Pack<uint8_t, VEC> *>(f + (long)i * a.pitch);
-#pragma unroll
-      for (int v = 0; v < VEC; ++v) any |= (v >= lo && v < hi) ? p.v[v] : 0u;
-    }
-  }
-  return __ballot(any != 0) == 0;
-}
-
-// True when the flags the wall-aware strip body loads for the strip at (chunk0,
-// y0) -- rows y0 - HALO .. y0 + NY + HALO - 1 of its 64 lanes' chunks, wrapped on a
-// periodic axis, SOLID outside a non-periodic x -- are the same in every row of
-// each column, and no row lies across a non-periodic y.  The body may then take the
-// flags of one row for all (COLF).  Wave-uniform.
-template <int VEC>
-__device__ __forceinline__ bool strip_colwall(const StepArgs &a, const int chunk0, const int y0, const int NY,
-                                              const int HALO) {
-  const bool py = a.periodic & 2u;
-  if (!py && (y0 < HALO || y0 + NY + HALO > a.ny)) return false;
-  const int lane = threadIdx.x & 63;
-  const int nch = (a.nx + VEC - 1) / VEC;
-  const int ch = chunk0 - 1 + lane;
-  int chw = ch;
-  bool col_ok = true;
-  if (ch < 0 || ch >= nch) {
-    if (a.periodic & 1u)
-      chw = ((ch % nch) + nch) % nch;
-    else
-      col_ok = false;  // read as SOLID in every row
-  }
-  uint32_t diff = 0;
-  if (col_ok) {
-    const uint8_t *f = a.flags + (long)chw * VEC;
-    const Pack<uint8_t, VEC> p0 =
-        *reinterpret_cast<const Pack<uint8_t, VEC> *>(f + (long)wrap_axis(y0 - HALO, a.ny, py) * a.pitch);
-    for (int i = 1; i < NY + 2 * HALO; ++i) {
-      const int rr = wrap_axis(y0 - HALO + i, a.ny, py);
-      const Pack<uint8_t, VEC> p = *reinterpret_cast<const Pack<uint8_t, VEC> *>(f + (long)rr * a.pitch);
-#pragma unroll
-      for (int v = 0; v < VEC; ++v) diff |= (uint32_t)(p.v[v] ^ p0.v[v]);
-    }
-  }
-  return __ballot(diff != 0) == 0;
-}
-
 // The kind of each strip of a work list: interior (the wall-free body), column
 // walls (the wall-aware body with the flags of one row) or neither.  A strip's
 // geometry does not change while its grid is resident, so this runs once per work

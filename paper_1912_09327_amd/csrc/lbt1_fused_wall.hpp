@@ -17,6 +17,7 @@
 // are those of the single-step strip kernel; the arithmetic and its order are
 // those of strip_body, so two fused steps give the bits of two single steps.
 #pragma once
+#include "lbt1_fused.hpp"
 #include "lbt1_step.hpp"
 
 namespace lbt1 {
@@ -273,13 +274,24 @@ __global__ void __launch_bounds__(256) k_step_fused_wall(StepArgs a, StripMap m)
     const int sy = s / m.strips_x;
     const int sx = s - sy * m.strips_x;
     if (sy >= m.strips_y) continue;
-    if constexpr (Traits<P>::kScaled) {
-      if (a.sc_d == 1.0 && a.sc_j == 1.0 && a.is_d == 1.0 && a.is_j == 1.0)  // wave-uniform
-        fused_wall_body<P, WALL, VEC, NY, true>(a, sx * 62, sy * NY, lane);
-      else
-        fused_wall_body<P, WALL, VEC, NY, false>(a, sx * 62, sy * NY, lane);
-    } else {
+    // a strip no wall, fixed node or grid edge reaches within two steps takes the
+    // wall-free two-step body (same bits; most strips of a large cavity).  Not in
+    // FP64, where the two bodies together would spill scalar registers.
+    const bool interior = P != P_F64 && strip_interior<VEC>(a, sx * 62, sy * NY, NY, 2);
+    const bool unit = !Traits<P>::kScaled || (a.sc_d == 1.0 && a.sc_j == 1.0 && a.is_d == 1.0 && a.is_j == 1.0);
+    if constexpr (P != P_F64) {
+      if (interior) {
+        if (unit)  // wave-uniform
+          fused_body<P, VEC, NY, 2, true>(a, sx * 62, sy * NY, lane);
+        else
+          fused_body<P, VEC, NY, 2, false>(a, sx * 62, sy * NY, lane);
+        continue;
+      }
+    }
+    if (unit) {
       fused_wall_body<P, WALL, VEC, NY, true>(a, sx * 62, sy * NY, lane);
+    } else {
+      fused_wall_body<P, WALL, VEC, NY, false>(a, sx * 62, sy * NY, lane);
     }
   }
 }

@@ -357,3 +357,37 @@ def test_strip_kinds_hold_what_their_bodies_assume(VEC, HALO):
                     elif strip_colwall(flags, per, VEC, c0, y0, NY, HALO):
                         seen["colwall"] += 1
     assert seen["interior"] > 0 and seen["colwall"] > 0
+
+
+@pytest.mark.parametrize("VEC", [2, 4])
+def test_interior_strips_of_walled_grids_stay_inside_without_wrapping(VEC):
+    """The walled two-step kernels hand interior strips (strip_interior, two steps)
+    to the wall-free body, which wraps chunks and rows as on a periodic grid and
+    takes nch = nx // VEC.  For such a strip every chunk its 64 lanes load and every
+    row it walks (NY + 4) lies inside the grid, so nothing wraps, and every stored
+    chunk lies below nx // VEC."""
+    from paper_1912_09327_amd import inputs as I
+    rng = np.random.default_rng(12)
+    geos = [I.cavity(L, 0.05)[0] for L in (61, 130, 263, 301, 517)]
+    geos.append(I.cavity(600, 0.05, ny=70)[0])
+    f = np.zeros((60, 530), np.uint8)
+    f[rng.random(f.shape) < 0.01] = I.SOLID
+    geos.append(f)
+    seen = 0
+    for flags in geos:
+        ny, nx = flags.shape
+        nch_ceil, nch_floor = -(-nx // VEC), nx // VEC
+        for NY in (2, 6, 14, 30):
+            for sy in range(-(-ny // NY)):
+                for sx in range(-(-nch_ceil // 62)):
+                    c0, y0 = sx * 62, sy * NY
+                    if not strip_interior(flags, 0, VEC, c0, y0, NY, 2):
+                        continue
+                    seen += 1
+                    ch = c0 - 1 + np.arange(64)
+                    assert (ch >= 0).all() and (ch < nch_floor).all()
+                    rows = y0 - 2 + np.arange(NY + 4)
+                    assert (rows >= 0).all() and (rows < ny).all()
+                    stored = ch[1:63]
+                    assert (stored[stored < nch_floor] == stored).all()
+    assert seen > 0
