@@ -671,7 +671,8 @@ lbt1_status lbt1_batch_autotune(lbt1_batch *b, int32_t burst_steps, int32_t reps
   lbt1_batch_shape bestsh{};
   double best_ms = 1e300;
   const int modes[] = {FUSE_NONE, FUSE_MIXED, FUSE_ALL};
-  for (int cap = CLS_V4; cap >= CLS_V2 && !st; --cap)
+  // every column cap (four, then two columns per lane), LDS mode and fuse mode
+  for (int cap = CLS_V4; cap >= CLS_V2 && !st; --cap) {
   for (int lds = 0; lds <= 1 && !st; ++lds) {
     for (int mode : modes) {
       if (st) break;
@@ -725,6 +726,7 @@ lbt1_status lbt1_batch_autotune(lbt1_batch *b, int32_t burst_steps, int32_t reps
         bestsh = cur;
       }
     }
+  }
   }
   (void)hipStreamSynchronize(b->stream);
   const hipError_t er = copy_all(false);
