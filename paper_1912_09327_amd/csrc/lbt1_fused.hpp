@@ -85,9 +85,70 @@ __device__ __forceinline__ void fused_feed(FusedStage<P, VEC> &st, const bool em
   }
 }
 
+// The same stage for a strip walked upwards (source rows in decreasing order):
+// a target row is completed by the row below it, its last source.  It keeps the
+// level sums of the pending target and the down-sums of the row above it apart
+// until then, so the target's sums are still formed as finish() forms them,
+// (row below + level) + row above: the same bits as the downward walk.
+template <int P, int VEC>
+struct FusedStageUp {
+  using C = typename Traits<P>::C;
+  C ls[VEC], lx[VEC];  // pending target row: level sums
+  C ps[VEC], px[VEC];  // and the down-sums of the row above it
+  C ns[VEC], nx[VEC];  // down-sums of the newest source row
+};
+
+template <int P, int VEC>
+__device__ __forceinline__ void fused_feed(FusedStageUp<P, VEC> &st, const bool emit_row,
+                                           const typename Traits<P>::C (&d)[VEC],
+                                           const typename Traits<P>::C (&jx)[VEC],
+                                           const typename Traits<P>::C (&jy)[VEC],
+                                           const typename Traits<P>::C (&Fx)[VEC],
+                                           const typename Traits<P>::C (&Fy)[VEC], typename Traits<P>::C (&dn)[VEC],
+                                           typename Traits<P>::C (&jxn)[VEC], typename Traits<P>::C (&jyn)[VEC]) {
+  using C = typename Traits<P>::C;
+  C f[VEC][9];
+#pragma unroll
+  for (int v = 0; v < VEC; ++v) emit<C>(d[v], jx[v], jy[v], Fx[v], Fy[v], f[v]);
+  const C L1 = lane_left<P>(f[VEC - 1][1]);
+  const C L5 = lane_left<P>(f[VEC - 1][5]);
+  const C L8 = lane_left<P>(f[VEC - 1][8]);
+  const C R3 = lane_right<P>(f[0][3]);
+  const C R6 = lane_right<P>(f[0][6]);
+  const C R7 = lane_right<P>(f[0][7]);
+#pragma unroll
+  for (int v = 0; v < VEC; ++v) {
+    // up-sums of this row complete the target row above it
+    const C a5 = v > 0 ? f[v - 1][5] : L5;
+    const C a2 = f[v][2];
+    const C a6 = v < VEC - 1 ? f[v + 1][6] : R6;
+    const C us = row_sum(a5, a2, a6), ux = row_dif(a5, a6);
+    if (emit_row) {
+      dn[v] = (us + st.ls[v]) + st.ps[v];
+      jxn[v] = (ux + st.lx[v]) + st.px[v];
+      jyn[v] = us - st.ps[v];
+    }
+    // this row becomes the pending target: its level sums, and the down-sums of
+    // the row above it (the previous source row)
+    const C a1 = v > 0 ? f[v - 1][1] : L1;
+    const C a0 = f[v][0];
+    const C a3 = v < VEC - 1 ? f[v + 1][3] : R3;
+    st.ls[v] = row_sum(a1, a0, a3);
+    st.lx[v] = row_dif(a1, a3);
+    st.ps[v] = st.ns[v];
+    st.px[v] = st.nx[v];
+    const C a8 = v > 0 ? f[v - 1][8] : L8;
+    const C a4 = f[v][4];
+    const C a7 = v < VEC - 1 ? f[v + 1][7] : R7;
+    st.ns[v] = row_sum(a8, a4, a7);
+    st.nx[v] = row_dif(a8, a7);
+  }
+}
+
 // UNIT: both storage scales are 1 (the default), so the codec's scaling
-// multiplications are exact no-ops and are left out.
-template <int P, int VEC, int NY, int K, bool UNIT>
+// multiplications are exact no-ops and are left out.  UP: the strip is walked
+// upwards, from its last halo row to its first (see k_step_fused).
+template <int P, int VEC, int NY, int K, bool UNIT, bool UP = false>
 __device__ __forceinline__ void fused_body(const StepArgs &a, const int chunk0, const int y0, const int lane) {
   using T = Traits<P>;
   using C = typename T::C;
@@ -121,7 +182,7 @@ __device__ __forceinline__ void fused_body(const StepArgs &a, const int chunk0, 
     SP raw[3];
   };
   auto load_row = [&](const int i, Row &dst) __attribute__((always_inline)) {
-    const long row = wrap_axis(y0 - K + i, ny, true);
+    const long row = wrap_axis(UP ? y0 + NY + K - 1 - i : y0 - K + i, ny, true);
     const long idx = row * rs + xc;
     dst.raw[0] = *reinterpret_cast<const SP *>(s0 + idx);
     dst.raw[1] = *reinterpret_cast<const SP *>(s1 + idx);
@@ -156,7 +217,8 @@ __device__ __forceinline__ void fused_body(const StepArgs &a, const int chunk0, 
     }
   };
 
-  FusedStage<P, VEC> stage[K] = {};
+  using Stage = typename std::conditional<UP, FusedStageUp<P, VEC>, FusedStage<P, VEC>>::type;
+  Stage stage[K] = {};
   // Two steps: one wavefront per SIMD is enough registers for a ring of rows
   // loaded two ahead.  Three steps: the kernel is built for two wavefronts per
   // SIMD, which leaves room for one row in flight ahead of the row being fed
@@ -189,7 +251,7 @@ __device__ __forceinline__ void fused_body(const StepArgs &a, const int chunk0, 
         if (s + 1 < K) {
           decode(out, d, jx, jy);
         } else {
-          const int t = y0 + i - 2 * K;  // row leaving the last stage
+          const int t = UP ? y0 + NY - 1 - (i - 2 * K) : y0 + i - 2 * K;  // row leaving the last stage
           const bool ok = t < ny && lane_out;
           const long idx = (long)t * rs + xc;
           S *trash = static_cast<S *>(a.trash) + lane * VEC;
@@ -229,6 +291,13 @@ k_step_fused(StepArgs a, StripMap m) {
         fused_body<P, VEC, NY, K, true>(a, sx * 62, sy * NY, lane);
       else
         fused_body<P, VEC, NY, K, false>(a, sx * 62, sy * NY, lane);
+    } else if (K >= 3 && (sy & 1)) {
+      // Three steps: odd row bands walk upwards.  A downward strip reads the halo
+      // rows it shares with the band below at the end of its walk and the band
+      // below reads them at the start of its own; with alternate directions two
+      // neighbouring bands read their shared rows at the same end of their walks,
+      // while the first copy is still in L2.
+      fused_body<P, VEC, NY, K, true, true>(a, sx * 62, sy * NY, lane);
     } else {
       fused_body<P, VEC, NY, K, true>(a, sx * 62, sy * NY, lane);
     }
