@@ -291,12 +291,13 @@ k_step_fused(StepArgs a, StripMap m) {
         fused_body<P, VEC, NY, K, true>(a, sx * 62, sy * NY, lane);
       else
         fused_body<P, VEC, NY, K, false>(a, sx * 62, sy * NY, lane);
-    } else if (K >= 3 && (sy & 1)) {
-      // Three steps: odd row bands walk upwards.  A downward strip reads the halo
-      // rows it shares with the band below at the end of its walk and the band
-      // below reads them at the start of its own; with alternate directions two
+    } else if (P == P_F32 && (sy & 1)) {
+      // FP32: odd row bands walk upwards.  A downward strip reads the halo rows it
+      // shares with the band below at the end of its walk and the band below
+      // reads them at the start of its own; with alternate directions two
       // neighbouring bands read their shared rows at the same end of their walks,
-      // while the first copy is still in L2.
+      // while the first copy is still in L2.  (FP64 strips, six rows tall by
+      // default, measured 3 % slower so; 16-bit storage is bound by arithmetic.)
       fused_body<P, VEC, NY, K, true, true>(a, sx * 62, sy * NY, lane);
     } else {
       fused_body<P, VEC, NY, K, true>(a, sx * 62, sy * NY, lane);
