@@ -405,10 +405,10 @@ enum {
 typedef struct {
   int32_t fuse;     /* LBT1_BATCH_FUSE_* */
   int32_t lds;      /* 1: grids that fit run resident in LDS (class 4); 0: they do not */
-  int32_t rows[5];  /* strip height of classes 0..4: 6 or 14 for classes 0-2 and 4; 2, 6,
-                       14 or 30 (not 30 in FP64) for class 3; 0 = the library's heuristic
-                       (14 rows where a class has eight or more strips per CU, else 6;
-                       class 3 30 rows where it has four or more such strips per CU) */
+  int32_t rows[5];  /* strip height of classes 0..4: 6, 14 or 30 (not 30 in FP64) for classes 0-2;
+                       2, 6, 14 or 30 (not 30 in FP64) for class 3; 6 or 14 for class 4; 0 = the
+                       library's heuristic (14 rows where a class has eight or more strips per CU,
+                       else 6; class 3 30 rows where it has four or more such strips per CU) */
   int32_t vec_cap;  /* widest columns per lane of the one-step classes: 4 (and 0: the
                        default), 2 or 1; narrower chunks hold fewer registers, so more
                        wavefronts per SIMD hide memory latency */

@@ -423,8 +423,10 @@ static lbt1_status set_shape(lbt1_batch *b, const lbt1_batch_shape &sh) {
   for (int c = 0; c < kClasses; ++c) {
     const int r = sh.rows[c];
     if (r == 0) continue;
-    const bool ok = c == CLS_F2 ? batch_fused_kernel(b->prec >= 0 ? b->prec : LBT1_F32, r) != nullptr
-                                : (r == 6 || r == 14);
+    const int pr = b->prec >= 0 ? b->prec : LBT1_F32;
+    const bool ok = c == CLS_F2    ? batch_fused_kernel(pr, r) != nullptr
+                    : c == CLS_LDS ? (r == 6 || r == 14)
+                                   : batch_step_kernel(pr, c, r) != nullptr;
     if (!ok) return fail(LBT1_EINVAL, "class %d: no built kernel with %d-row strips", c, r);
   }
   b->fuse_mode = sh.fuse;
@@ -704,15 +706,16 @@ lbt1_status lbt1_batch_autotune(lbt1_batch *b, int32_t burst_steps, int32_t reps
       // coordinate descent over the strip height of each class present
       for (int c = 0; c < kClasses && !st; ++c) {
         if (!present[c]) continue;
-        const int single[] = {6, 14};
+        const int single[] = {6, 14, 30};
         const int fused[] = {2, 6, 14, 30};
         const int *opts = c == CLS_F2 ? fused : single;
-        const int nopt = c == CLS_F2 ? 4 : 2;
+        const int nopt = c == CLS_F2 ? 4 : c == CLS_LDS ? 2 : 3;
         int keep = cur.rows[c];
         for (int k = 0; k < nopt && !st; ++k) {
           lbt1_batch_shape t = cur;
           t.rows[c] = opts[k];
           if (c == CLS_F2 && !batch_fused_kernel(b->prec, opts[k])) continue;
+          if (c < CLS_F2 && !batch_step_kernel(b->prec, c, opts[k])) continue;
           const double ms = time_shape(t);
           if (ms < cur_ms) {
             cur_ms = ms;

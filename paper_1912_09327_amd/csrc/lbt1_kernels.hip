@@ -180,8 +180,8 @@ const void *bgk_reduce_partial_kernel(int prec) {
 }
 
 // Batched kernels (always wall-aware): [precision][vec class 0..2 = vec 1, 2, 4]
-// for strips of 14 rows (tall) and 6 rows (short: half the serial latency of a
-// strip, for classes with too few strips to fill the device).
+// for strips of 14 rows (tall), 6 rows (short: half the serial latency of a
+// strip, for classes with too few strips to fill the device) and 30 rows.
 #define BATCH_ROW(P, R) \
   {(const void *)&k_step_batch<P, 1, R>, (const void *)&k_step_batch<P, 2, R>, (const void *)&k_step_batch<P, 4, R>, nullptr}
 
@@ -198,9 +198,17 @@ const void *batch_step_kernel(int prec, int vec_class, int rows) {
       BATCH_ROW(P_F16S, 6),
       BATCH_ROW(P_BF16S, 6),
   };
+  // 30-row strips: fewer, longer walks per item (not FP64, whose 30-row strips spill)
+  static const void *tall30[4][4] = {
+      {nullptr, nullptr, nullptr, nullptr},
+      BATCH_ROW(P_F32, 30),
+      BATCH_ROW(P_F16S, 30),
+      BATCH_ROW(P_BF16S, 30),
+  };
   if (prec < 0 || prec > 3 || vec_class < 0 || vec_class > 3) return nullptr;
   if (rows == 14) return tall[prec][vec_class];
   if (rows == 6) return shrt[prec][vec_class];
+  if (rows == 30) return tall30[prec][vec_class];
   return nullptr;
 }
 
