@@ -334,9 +334,12 @@ lbt1_status lbt1_grid3d_read_moments(lbt1_grid3d *g, double *rho, double *jx, do
  * 5 non-finite count, 6 FLUID count, 7 zero.  Synchronises. */
 lbt1_status lbt1_grid3d_reduce(lbt1_grid3d *g, uint32_t what, double *out);
 /* Kernel family: LBT1_KERNEL_AUTO (default) and LBT1_KERNEL_STRIP take the tile
- * kernel (a 64 x 8 block marches along z with three planes of per-node values
- * in LDS, and their flags on grids with SOLID or FIXED nodes or a non-periodic
- * axis); LBT1_KERNEL_GATHER one thread per node.  The two give the same bits.
+ * kernel (a block of 8 rows marches along z with three planes of per-node
+ * values in LDS: a wavefront holds 64 targets of a row and the block a halo
+ * ring, with the flags in LDS on grids with SOLID or FIXED nodes or a
+ * non-periodic axis; for D3Q27 on grids with every axis periodic and no SOLID
+ * or FIXED node, 62 targets and 2 halo columns, the x neighbours taken by lane
+ * shifts); LBT1_KERNEL_GATHER one thread per node.  They give the same bits.
  * get_kernel reports the family bound (ESTATE before set_geometry). */
 lbt1_status lbt1_grid3d_set_kernel(lbt1_grid3d *g, int32_t kernel);
 lbt1_status lbt1_grid3d_get_kernel(lbt1_grid3d *g, int32_t *kernel);

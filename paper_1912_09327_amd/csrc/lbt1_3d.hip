@@ -85,6 +85,7 @@ constexpr int kTile3Y = 8;   // rows of a tile block (64 x 8 nodes, 512 threads)
 static const void *tile3_kernel(int prec, int q, bool haswall, int wall) {
 #define T3(P, Q)                                                                                          \
   if (prec == P && q == Q) {                                                                              \
+    if (!haswall && Q == 27) return (const void *)&k_step3_lane<P, Q, zchunk_of<P>(), kTile3Y>;          \
     if (!haswall) return (const void *)&k_step3_tile<P, Q, zchunk_of<P>(), kTile3Y>;                     \
     return wall == WALL_PAPER ? (const void *)&k_step3_tile<P, Q, zchunk_of<P>(), kTile3Y, true, WALL_PAPER> \
                               : (const void *)&k_step3_tile<P, Q, zchunk_of<P>(), kTile3Y, true, WALL_HALFWAY>; \
@@ -131,8 +132,15 @@ struct lbt1_grid3d {
   const void *kern = nullptr;
 };
 
-// AUTO and STRIP take the tile kernel (its wall-aware form on grids with SOLID or
-// FIXED nodes or a non-periodic axis); GATHER the one-thread-per-node kernel.
+// AUTO and STRIP take a tile kernel: on fully periodic grids without SOLID or
+// FIXED nodes k_step3_lane for D3Q27 (at 512^3, FP32: 112.2k against 107.6k
+// MLUPS for k_step3_tile) and k_step3_tile for D3Q19 (137.3k against 105.2k: its
+// 64-column tiles divide the power-of-two sides, while 62-column tiles leave
+// 12.5 % of the lanes idle at 512, and D3Q19 reads too little from LDS to gain
+// from the lane shifts); k_step3_tile's wall-aware form otherwise.  GATHER: the
+// one-thread-per-node kernel.
+static bool lane3(const lbt1_grid3d *g) { return g->tile && !g->haswall && g->q == 27; }
+
 static lbt1_status bind3(lbt1_grid3d *g) {
   g->tile = g->want != LBT1_KERNEL_GATHER;
   g->kern = g->tile ? tile3_kernel(g->prec, g->q, g->haswall, g->wall) : step3_kernel(g->prec, g->q, g->haswall, g->wall);
@@ -348,7 +356,8 @@ lbt1_status lbt1_grid3d_step(lbt1_grid3d *g, int64_t n) {
   const dim3 block = g->tile ? dim3(64 * kTile3Y, 1, 1) : dim3(64, 4, 1);
   // tile kernel: one block per tile, rounded up to a multiple of the 8 XCDs (the
   // kernel maps block b to a tile of XCD b % 8's contiguous range)
-  const long ntiles = (long)((g->nx + kTile3X - 1) / kTile3X) * ((g->ny + kTile3Y - 1) / kTile3Y) *
+  const int tw = lane3(g) ? kLane3X : kTile3X;  // target columns per tile
+  const long ntiles = (long)((g->nx + tw - 1) / tw) * ((g->ny + kTile3Y - 1) / kTile3Y) *
                       ((g->nz + zchunk_for(g->prec) - 1) / zchunk_for(g->prec));
   const dim3 grid = g->tile ? dim3((unsigned)((ntiles + 7) / 8 * 8), 1, 1) : dim3((g->nx + 63) / 64, (g->ny + 3) / 4, g->nz);
   for (int64_t s = 0; s < n; ++s) {

@@ -352,6 +352,118 @@ __global__ void __launch_bounds__(64 * TY) k_step3_tile(Step3Args a) {
   }
 }
 
+// Grids with every axis periodic and every node FLUID: the same march along z,
+// with the x neighbours taken across the wavefront instead of from LDS.  A
+// wavefront holds one row of 64 nodes, x0 - 1 ... x0 + 62: lanes 1 to 62 are
+// the targets, lanes 0 and 63 the halo columns.  LDS holds three planes of
+// TY + 2 such rows (the tile rows and one halo row on either side, loaded by
+// wavefronts 0 and 1).  For each of the nine (e_y, e_z) offsets a lane reads the
+// per-source values of node (x, y - e_y, z - e_z) once and forms the emissions
+// of every direction with that offset; an emission along a direction with
+// e_x = +1 (-1) then moves one lane up (down) by a whole-wavefront DPP shift.
+// Half the LDS reads of the tile kernel for the same arithmetic in the same
+// summation order, so the two give the same bits.  Every lane takes part in
+// every shift (the halo lanes' emissions are what lanes 1 and 62 receive); only
+// the stores are guarded.
+constexpr int kLane3X = 62;
+
+template <int P, int Q, int ZC, int TY>
+__global__ void __launch_bounds__(64 * TY) k_step3_lane(Step3Args a) {
+  using T = Traits<P>;
+  using C = typename T::C;
+  using S = typename T::S;
+  constexpr int HY = TY + 2, HN = 64 * HY;
+  __shared__ C sJx[3][HN], sJy[3][HN], sJz[3][HN], sS[3][HN], sB[3][HN];
+  const int tid = threadIdx.x;
+  const int tx = tid & 63, ty = tid >> 6;
+  // tile order as in k_step3_tile (XCD b % 8 takes a contiguous range)
+  const int ntx = (a.nx + kLane3X - 1) / kLane3X, nty = (a.ny + TY - 1) / TY, ntz = (a.nz + ZC - 1) / ZC;
+  const int ntiles = ntx * nty * ntz, per = (ntiles + 7) / 8;
+  const int tile = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+  if (tile >= ntiles) return;  // uniform across the block
+  const int tz = tile / (ntx * nty), trow = tile - tz * ntx * nty, tyi = trow / ntx, txi = trow - tyi * ntx;
+  const int x0 = txi * kLane3X, y0 = tyi * TY, z0 = tz * ZC;
+  const C Fx = C(a.fx), Fy = C(a.fy), Fz = C(a.fz);
+  const int x = x0 - 1 + tx, y = y0 + ty;
+  const long xo = wrap_axis(x, a.nx, true);
+  const long own_off = (long)wrap_axis(y, a.ny, true) * a.rs + xo;
+  const int own_h = (ty + 1) * 64 + tx;
+  const bool has_halo = tid < 128;  // wavefront 0: row y0 - 1, wavefront 1: row y0 + TY
+  const int halo_h = tid < 64 ? tx : (HY - 1) * 64 + tx;
+  const long halo_off = (long)wrap_axis(tid < 64 ? y0 - 1 : y0 + TY, a.ny, true) * a.rs + xo;
+  C od, ojx, ojy, ojz, rd = C(0), rjx = C(0), rjy = C(0), rjz = C(0);
+  auto fetch = [&](const int z) __attribute__((always_inline)) {
+    const long zo = (long)wrap_axis(z, a.nz, true) * a.zs;
+    load3<P>(a, zo + own_off, od, ojx, ojy, ojz);
+    if (has_halo) load3<P>(a, zo + halo_off, rd, rjx, rjy, rjz);
+  };
+  auto put = [&](const C d, const C jx, const C jy, const C jz, const int slot, const int h)
+      __attribute__((always_inline)) {
+    const C inv = recip<C>(C(1) + d);
+    const C Jx = jx + Fx, Jy = jy + Fy, Jz = jz + Fz;
+    const C t = (Jx * Jx + Jy * Jy + Jz * Jz) * inv;
+    sJx[slot][h] = Jx;
+    sJy[slot][h] = Jy;
+    sJz[slot][h] = Jz;
+    sS[slot][h] = C(4.5) * inv;
+    sB[slot][h] = fmaC<C>(C(-1.5), t, d);
+  };
+  auto store_plane = [&](const int slot) __attribute__((always_inline)) {
+    put(od, ojx, ojy, ojz, slot, own_h);
+    if (has_halo) put(rd, rjx, rjy, rjz, slot, halo_h);
+  };
+  fetch(z0 - 1);
+  store_plane(0);
+  fetch(z0);
+  store_plane(1);
+  fetch(z0 + 1);
+  const bool out = tx >= 1 && tx <= kLane3X && x < a.nx && y < a.ny;
+  for (int k = 0; k < ZC; ++k) {
+    const int z = z0 + k;
+    if (z >= a.nz) break;  // uniform across the block
+    store_plane((k + 2) % 3);  // plane z + 1
+    if (k + 1 < ZC) fetch(z + 2);
+    __syncthreads();
+    C f[Q];
+#pragma unroll
+    for (int p = 0; p < 9; ++p) {
+      const int ey = p / 3 - 1, ez = p % 3 - 1;
+      const int slot = (k + 1 - ez + 3) % 3;  // plane z - e_z
+      const int h = (ty + 1 - ey) * 64 + tx;  // row y - e_y, this lane's column
+      const C Jx = sJx[slot][h], Jy = sJy[slot][h], Jz = sJz[slot][h], s = sS[slot][h], b = sB[slot][h];
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        if (k3y[q] != ey || k3z[q] != ez) continue;
+        const C e = emit3_sb<C, Q>(q, Jx, Jy, Jz, s, b);
+        f[q] = k3x[q] == 1 ? dpp_shift<kDppWaveShr1>(e) : k3x[q] == -1 ? dpp_shift<kDppWaveShl1>(e) : e;
+      }
+    }
+    C dn = C(0), xn = C(0), yn = C(0), zn = C(0);
+    bool hx = false, hy = false, hz = false;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      dn = q == 0 ? f[q] : dn + f[q];
+      acc_comp<C>(xn, hx, k3x[q], f[q]);
+      acc_comp<C>(yn, hy, k3y[q], f[q]);
+      acc_comp<C>(zn, hz, k3z[q], f[q]);
+    }
+    if (out) {
+      if (T::kScaled) {
+        dn *= C(a.is_d);
+        xn *= C(a.is_j);
+        yn *= C(a.is_j);
+        zn *= C(a.is_j);
+      }
+      const long i = (long)z * a.zs + (long)y * a.rs + x;
+      static_cast<S *>(a.dst[0])[i] = T::enc(dn);
+      static_cast<S *>(a.dst[1])[i] = T::enc(xn);
+      static_cast<S *>(a.dst[2])[i] = T::enc(yn);
+      static_cast<S *>(a.dst[3])[i] = T::enc(zn);
+    }
+    __syncthreads();  // the slot of plane z - 1 is refilled next
+  }
+}
+
 struct Reduce3Args {
   const void *cur[4];
   void *snap[4];

@@ -128,12 +128,12 @@ def test_3d_errors():
 
 @pytest.mark.parametrize("q", [19, 27])
 @pytest.mark.parametrize("prec", ["f64", "f32", "f16s"])
-@pytest.mark.parametrize("shape", [(9, 21, 70), (16, 4, 64), (20, 7, 130), (1, 3, 5)])
+@pytest.mark.parametrize("shape", [(9, 21, 70), (16, 4, 64), (20, 7, 130), (1, 3, 5), (40, 9, 124)])
 @pytest.mark.parametrize("kind,wall", [("periodic", "paper"), ("box", "paper"), ("box", "halfway"),
                                        ("plates", "paper"), ("plates", "halfway"), ("open", "halfway")])
 def test_3d_tile_bitwise_equals_gather(kind, wall, shape, prec, q):
-    """The tile kernel, with walls, fixed nodes and non-periodic axes as well, gives the
-    bits of one thread per node."""
+    """The tile kernels (lane exchange on periodic grids; walls, fixed nodes and
+    non-periodic axes as well) give the bits of one thread per node."""
     from paper_1912_09327_amd.grid3d import Grid3D
     if kind == "box" and min(shape) < 3:
         pytest.skip("a box needs three nodes along every axis")

@@ -3,8 +3,9 @@
 A Python restatement of the index arithmetic of every strip-shaped kernel that
 is built -- the single-step strip (k_step_strip), the fused periodic kernels
 (k_step_fused, K = 2 and 3), the fused kernel with walls (k_step_fused_wall),
-the multiphase strips (k_step_sc_strip, k_step_sc_fused) and the batched kernel
-(k_step_batch over its flattened item lists) -- checks, for many shapes and
+the multiphase strips (k_step_sc_strip, k_step_sc_fused), the batched kernel
+(k_step_batch over its flattened item lists) and the 3-D lane-exchange tiles
+(k_step3_lane) -- checks, for many shapes and
 every launch configuration, that
 
   * every moment load lies inside the parity block it reads,
@@ -391,3 +392,47 @@ def test_interior_strips_of_walled_grids_stay_inside_without_wrapping(VEC):
                     stored = ch[1:63]
                     assert (stored[stored < nch_floor] == stored).all()
     assert seen > 0
+
+
+@pytest.mark.parametrize("nx,ny,nz,zc", [(70, 21, 9, 32), (64, 4, 16, 32), (130, 7, 20, 16), (5, 3, 1, 32),
+                                         (124, 9, 40, 32), (62, 8, 33, 16), (512, 512, 64, 32)])
+def test_3d_lane_tiles_write_every_node_once(nx, ny, nz, zc):
+    """k_step3_lane (fully periodic 3-D grids): tiles of 62 target columns, 8 rows and
+    zc planes, one block of 8 wavefronts each, launched as the tile count rounded up to
+    a multiple of 8 blocks, block b taking tile (b % 8) * per + b // 8.  Lane l of the
+    wavefront of row y0 + w holds column x0 - 1 + l (lanes 1 to 62 are targets, lanes
+    0 and 63 halo columns).  Every tile is taken once, every load (own row, the halo
+    rows y0 - 1 and y0 + 8 of wavefronts 0 and 1, planes z0 - 1 to z0 + zc) wraps into
+    the grid, the lanes a target's x neighbours come from exist, and every node is
+    stored exactly once."""
+    TY, W = 8, 62
+    ntx, nty, ntz = -(-nx // W), -(-ny // TY), -(-nz // zc)
+    ntiles = ntx * nty * ntz
+    per = -(-ntiles // 8)
+    count = np.zeros((nz, ny, nx), np.int32)
+    taken = np.zeros(ntiles, np.int32)
+    lane = np.arange(64)
+    for b in range(-(-ntiles // 8) * 8):
+        tile = (b & 7) * per + (b >> 3)
+        if tile >= ntiles:
+            continue
+        taken[tile] += 1
+        tz, trow = divmod(tile, ntx * nty)
+        tyi, txi = divmod(trow, ntx)
+        x0, y0, z0 = txi * W, tyi * TY, tz * zc
+        x = x0 - 1 + lane
+        xl = wrap_axis(x, nx, True)
+        assert ((xl >= 0) & (xl < nx)).all()
+        for yy in (y0 - 1, y0 + TY, *range(y0, y0 + TY)):
+            assert 0 <= wrap_axis(yy, ny, True) < ny
+        zs = wrap_axis(np.arange(z0 - 1, z0 + zc + 1), nz, True)
+        assert ((zs >= 0) & (zs < nz)).all()
+        tgt = (lane >= 1) & (lane <= W) & (x < nx)
+        assert ((lane[tgt] - 1 >= 0) & (lane[tgt] + 1 <= 63)).all()
+        z1 = min(z0 + zc, nz)
+        for w in range(TY):
+            y = y0 + w
+            if y < ny:
+                count[z0:z1, y, x[tgt]] += 1
+    assert (taken == 1).all()
+    assert (count == 1).all()
