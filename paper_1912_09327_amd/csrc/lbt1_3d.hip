@@ -72,14 +72,19 @@ static const void *step3_kernel(int prec, int q, bool haswall, int wall) {
   return nullptr;
 }
 
-// Planes a tile block marches through: 32 with 4- and 8-byte storage, 16 with
+// Planes a tile block marches through: 32, but 16 for the periodic kernels with
 // 16-bit storage (at 512^3, D3Q19: FP32 126.9k against 123.7k MLUPS at 16;
-// FP16S 131.0k against 137.1k at 32).
+// FP16S 131.0k against 137.1k at 32).  The wall-aware kernels take 32 in every
+// storage (FP16S lid-driven box at 512^3: 80.7k against 76.5k MLUPS at 16, and
+// 96 VGPRs against 116).
 template <int P>
 constexpr int zchunk_of() {
   return P == P_F16S || P == P_BF16S ? 16 : 32;
 }
-static int zchunk_for(int prec) { return prec == P_F16S || prec == P_BF16S ? 16 : 32; }
+constexpr int kZChunkWall = 32;
+static int zchunk_for(int prec, bool haswall) {
+  return haswall ? kZChunkWall : prec == P_F16S || prec == P_BF16S ? 16 : 32;
+}
 constexpr int kTile3Y = 8;   // rows of a tile block (64 x 8 nodes, 512 threads)
 
 static const void *tile3_kernel(int prec, int q, bool haswall, int wall) {
@@ -87,8 +92,8 @@ static const void *tile3_kernel(int prec, int q, bool haswall, int wall) {
   if (prec == P && q == Q) {                                                                              \
     if (!haswall && Q == 27) return (const void *)&k_step3_lane<P, Q, zchunk_of<P>(), kTile3Y>;          \
     if (!haswall) return (const void *)&k_step3_tile<P, Q, zchunk_of<P>(), kTile3Y>;                     \
-    return wall == WALL_PAPER ? (const void *)&k_step3_tile<P, Q, zchunk_of<P>(), kTile3Y, true, WALL_PAPER> \
-                              : (const void *)&k_step3_tile<P, Q, zchunk_of<P>(), kTile3Y, true, WALL_HALFWAY>; \
+    return wall == WALL_PAPER ? (const void *)&k_step3_tile<P, Q, kZChunkWall, kTile3Y, true, WALL_PAPER> \
+                              : (const void *)&k_step3_tile<P, Q, kZChunkWall, kTile3Y, true, WALL_HALFWAY>; \
   }
   T3(P_F64, 19) T3(P_F64, 27) T3(P_F32, 19) T3(P_F32, 27) T3(P_F16S, 19) T3(P_F16S, 27) T3(P_BF16S, 19)
   T3(P_BF16S, 27)
@@ -358,7 +363,7 @@ lbt1_status lbt1_grid3d_step(lbt1_grid3d *g, int64_t n) {
   // kernel maps block b to a tile of XCD b % 8's contiguous range)
   const int tw = lane3(g) ? kLane3X : kTile3X;  // target columns per tile
   const long ntiles = (long)((g->nx + tw - 1) / tw) * ((g->ny + kTile3Y - 1) / kTile3Y) *
-                      ((g->nz + zchunk_for(g->prec) - 1) / zchunk_for(g->prec));
+                      ((g->nz + zchunk_for(g->prec, g->haswall) - 1) / zchunk_for(g->prec, g->haswall));
   const dim3 grid = g->tile ? dim3((unsigned)((ntiles + 7) / 8 * 8), 1, 1) : dim3((g->nx + 63) / 64, (g->ny + 3) / 4, g->nz);
   for (int64_t s = 0; s < n; ++s) {
     Step3Args a = step3_args(g, g->parity);
