@@ -117,6 +117,35 @@ __device__ __forceinline__ void load3(const Step3Args &a, long i, typename Trait
   }
 }
 
+// load3 in two halves: the stored values of node i, and their decoding (the same
+// operations in the same order).  The tile kernels keep a plane's stored values
+// in registers while its loads are in flight and decode them only when the plane
+// goes to LDS, one plane later, so no wait for the loads is forced before the
+// targets of the current plane are formed.
+template <int P>
+__device__ __forceinline__ void load3_raw(const Step3Args &a, long i, typename Traits<P>::S &d, typename Traits<P>::S &jx,
+                                          typename Traits<P>::S &jy, typename Traits<P>::S &jz) {
+  using S = typename Traits<P>::S;
+  d = static_cast<const S *>(a.src[0])[i];
+  jx = static_cast<const S *>(a.src[1])[i];
+  jy = static_cast<const S *>(a.src[2])[i];
+  jz = static_cast<const S *>(a.src[3])[i];
+}
+template <int P>
+__device__ __forceinline__ typename Traits<P>::C dec3_d(const Step3Args &a, typename Traits<P>::S v) {
+  using C = typename Traits<P>::C;
+  C d = Traits<P>::dec(v);
+  if (Traits<P>::kScaled) d *= C(a.sc_d);
+  return d;
+}
+template <int P>
+__device__ __forceinline__ typename Traits<P>::C dec3_j(const Step3Args &a, typename Traits<P>::S v) {
+  using C = typename Traits<P>::C;
+  C j = Traits<P>::dec(v);
+  if (Traits<P>::kScaled) j *= C(a.sc_j);
+  return j;
+}
+
 // One thread per node; blocks of 64 x 4 nodes in (x, y), grid (x tiles,
 // y tiles, nz).
 template <int P, int Q, bool HASWALL, int WALL>
@@ -263,21 +292,22 @@ __global__ void __launch_bounds__(64 * TY) k_step3_tile(Step3Args a) {
   // plane loads run one plane ahead in registers: the loads of plane z + 2 are
   // in flight while the targets of plane z are formed.  Positions outside a
   // non-periodic axis load node 0 and are flagged SOLID.
-  C od, ojx, ojy, ojz, rd = C(0), rjx = C(0), rjy = C(0), rjz = C(0);
+  S od, ojx, ojy, ojz, rd = S(0), rjx = S(0), rjy = S(0), rjz = S(0);  // stored values (see load3_raw)
   uint8_t ofl = NODE_FLUID, rfl = NODE_FLUID;
   auto fetch = [&](const int z) __attribute__((always_inline)) {
     const int wz = wrap_axis(z, a.nz, pz);
     const long zo = wz < 0 ? 0 : (long)wz * a.zs;
-    load3<P>(a, zo + (own_off < 0 ? 0 : own_off), od, ojx, ojy, ojz);
-    if (has_ring) load3<P>(a, zo + (ring_off < 0 ? 0 : ring_off), rd, rjx, rjy, rjz);
+    load3_raw<P>(a, zo + (own_off < 0 ? 0 : own_off), od, ojx, ojy, ojz);
+    if (has_ring) load3_raw<P>(a, zo + (ring_off < 0 ? 0 : ring_off), rd, rjx, rjy, rjz);
     if (HASWALL) {
       const long fz = (long)(wz < 0 ? 0 : wz) * a.fzs;
       ofl = wz < 0 || own_foff < 0 ? (uint8_t)NODE_SOLID : a.flags[fz + own_foff];
       if (has_ring) rfl = wz < 0 || ring_foff < 0 ? (uint8_t)NODE_SOLID : a.flags[fz + ring_foff];
     }
   };
-  auto put = [&](const C d, const C jx, const C jy, const C jz, const int slot, const int h)
+  auto put = [&](const S sd, const S sjx, const S sjy, const S sjz, const int slot, const int h)
       __attribute__((always_inline)) {
+    const C d = dec3_d<P>(a, sd), jx = dec3_j<P>(a, sjx), jy = dec3_j<P>(a, sjy), jz = dec3_j<P>(a, sjz);
     const C inv = recip<C>(C(1) + d);
     const C Jx = jx + Fx, Jy = jy + Fy, Jz = jz + Fz;
     const C t = (Jx * Jx + Jy * Jy + Jz * Jz) * inv;
@@ -300,7 +330,7 @@ __global__ void __launch_bounds__(64 * TY) k_step3_tile(Step3Args a) {
   store_plane(0);
   fetch(z0);
   store_plane(1);
-  C own_d = od;      // the target's own deviation (plane z), for the wall rule
+  C own_d = dec3_d<P>(a, od);  // the target's own deviation (plane z), for the wall rule
   uint8_t own_fl = ofl;
   fetch(z0 + 1);
   const int x = x0 + tx, y = y0 + ty;
@@ -309,7 +339,7 @@ __global__ void __launch_bounds__(64 * TY) k_step3_tile(Step3Args a) {
     const int z = z0 + k;
     if (z >= a.nz) break;  // uniform across the block
     store_plane((k + 2) % 3);  // plane z + 1
-    const C next_d = od;
+    const C next_d = dec3_d<P>(a, od);
     const uint8_t next_fl = ofl;
     if (k + 1 < ZC) fetch(z + 2);
     __syncthreads();
@@ -391,14 +421,15 @@ __global__ void __launch_bounds__(64 * TY) k_step3_lane(Step3Args a) {
   const bool has_halo = tid < 128;  // wavefront 0: row y0 - 1, wavefront 1: row y0 + TY
   const int halo_h = tid < 64 ? tx : (HY - 1) * 64 + tx;
   const long halo_off = (long)wrap_axis(tid < 64 ? y0 - 1 : y0 + TY, a.ny, true) * a.rs + xo;
-  C od, ojx, ojy, ojz, rd = C(0), rjx = C(0), rjy = C(0), rjz = C(0);
+  S od, ojx, ojy, ojz, rd = S(0), rjx = S(0), rjy = S(0), rjz = S(0);  // stored values (see load3_raw)
   auto fetch = [&](const int z) __attribute__((always_inline)) {
     const long zo = (long)wrap_axis(z, a.nz, true) * a.zs;
-    load3<P>(a, zo + own_off, od, ojx, ojy, ojz);
-    if (has_halo) load3<P>(a, zo + halo_off, rd, rjx, rjy, rjz);
+    load3_raw<P>(a, zo + own_off, od, ojx, ojy, ojz);
+    if (has_halo) load3_raw<P>(a, zo + halo_off, rd, rjx, rjy, rjz);
   };
-  auto put = [&](const C d, const C jx, const C jy, const C jz, const int slot, const int h)
+  auto put = [&](const S sd, const S sjx, const S sjy, const S sjz, const int slot, const int h)
       __attribute__((always_inline)) {
+    const C d = dec3_d<P>(a, sd), jx = dec3_j<P>(a, sjx), jy = dec3_j<P>(a, sjy), jz = dec3_j<P>(a, sjz);
     const C inv = recip<C>(C(1) + d);
     const C Jx = jx + Fx, Jy = jy + Fy, Jz = jz + Fz;
     const C t = (Jx * Jx + Jy * Jy + Jz * Jz) * inv;
